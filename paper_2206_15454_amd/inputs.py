@@ -1,0 +1,142 @@
+"""Seeded synthetic inputs and the workload table.
+
+This module holds no arithmetic of the method: only the sizes and physical
+parameters of each workload and the seeded initial fields (density and
+velocity).  It is the one module that both the oracle-based tests and the
+GPU path read, so that both sides start from identical arrays.
+
+Initial velocity (every workload): u_x = U_ref (y_j / Y)^(1/7) + A U_ref xi_x,
+u_y = A U_ref xi_y, u_z = A U_ref xi_z, with xi ~ U[-1, 1) drawn i.i.d. per
+cell and component by NumPy's PCG64 generator (``default_rng(seed)``) as one
+array of shape (3, nz, ny, nx) in C order; y_j = j + 1/2; rho = 1 exactly.
+
+Leaf-area density: a workload names either a constant value below a canopy
+row (``lad_const``, ``canopy_rows``) or the Lalic-Mihailovic profile by its
+parameters (``lad_lalic``: h, y_m, LAI); the caller evaluates the profile with
+its own implementation of the paper's Eq. (af_theory).
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP = 0, 1, 2
+STORAGES = ("f64", "f32", "f16s", "bf16s")
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    storage: str
+    tau0: float
+    c_smag: float
+    g: Tuple[float, float, float]
+    bc_lo: int
+    bc_hi: int
+    cd: float
+    lad_const: float = 0.0
+    canopy_rows: int = 0
+    lad_lalic: Optional[Tuple[float, float, float]] = None  # (h, y_m, LAI) in cells
+    u_ref: float = 0.05
+    y_ref: float = 32.0
+    noise: float = 0.02
+    seed: int = 1
+    steps: int = 200
+    extra: dict = field(default_factory=dict, compare=False, hash=False)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+
+# canopy boundary layer, plain method in FP64: 64x32x32, 200 steps
+C1 = Workload(name="canopy-abl-64x32x32-f64", nx=64, ny=32, nz=32, storage="f64", tau0=0.52,
+              c_smag=0.01, g=(1e-6, 0.0, 0.0), bc_lo=BC_BOUNCEBACK, bc_hi=BC_FREESLIP, cd=0.2,
+              lad_const=0.3, canopy_rows=8, u_ref=0.05, y_ref=32.0, noise=0.02, seed=1,
+              steps=200)
+
+# production canopy boundary layer in FP32: 512x128x256, h = 12, LAI 2, u_tau = 0.01
+C2 = Workload(name="canopy-abl-512x128x256-f32", nx=512, ny=128, nz=256, storage="f32",
+              tau0=0.5005, c_smag=0.01, g=(0.01 ** 2 / 128.0, 0.0, 0.0),
+              bc_lo=BC_BOUNCEBACK, bc_hi=BC_FREESLIP, cd=0.15, lad_lalic=(12.0, 8.4, 2.0),
+              u_ref=0.1, y_ref=128.0, noise=0.05, seed=2, steps=20000)
+
+# precision study: physics of the 64x32x32 case on 1024x256x512 cells
+C3 = replace(C1, name="canopy-abl-1024x256x512", nx=1024, ny=256, nz=512, storage="f32",
+             seed=3, steps=1000)
+
+# the same physics on a 128x64x64 crop that the oracle finishes
+CROP = replace(C1, name="canopy-abl-128x64x64", nx=128, ny=64, nz=64, seed=3, steps=1000)
+
+# learned-closure training data: the production setup at twice the resolution
+# (acoustic scaling in coarse units: tau0_f = 1/2 + 2 (tau0 - 1/2), g_f = g / 2)
+C4 = replace(C2, name="canopy-abl-fine-1024x256x512-f32", nx=1024, ny=256, nz=512,
+             tau0=0.501, g=(C2.g[0] / 2.0, 0.0, 0.0), lad_lalic=(24.0, 16.8, 2.0),
+             y_ref=256.0, seed=4, steps=40000)
+
+# learned-closure inference: 1024x256x512 BF16 storage
+C5 = replace(C3, name="canopy-abl-1024x256x512-bf16s-mlp", storage="bf16s", seed=3,
+             steps=20000)
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5)}
+
+
+def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
+    """The same physics on another grid (test sizes)."""
+    return replace(w, name=f"{w.name}@{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, **kw)
+
+
+def lad_constant(w: Workload) -> Optional[np.ndarray]:
+    """Constant-LAD canopy rows (None when the workload uses the profile)."""
+    if w.lad_lalic is not None:
+        return None
+    lad = np.zeros(w.ny)
+    lad[: min(w.canopy_rows, w.ny)] = w.lad_const
+    return lad
+
+
+def init_fields(w: Workload, seed: Optional[int] = None):
+    """Seeded initial density and velocity, float64, shapes (nz,ny,nx) and
+    (3,nz,ny,nx)."""
+    rng = np.random.default_rng(w.seed if seed is None else seed)
+    xi = rng.uniform(-1.0, 1.0, size=(3,) + w.shape)
+    y = np.arange(w.ny, dtype=np.float64) + 0.5
+    ubar = w.u_ref * (y / w.y_ref) ** (1.0 / 7.0)
+    u = w.noise * w.u_ref * xi
+    u[0] += ubar[None, :, None]
+    rho = np.ones(w.shape)
+    return rho, u
+
+
+def init_fields_torch(w: Workload, device, seed: Optional[int] = None):
+    """The same recipe drawn on the GPU with torch's generator (for grids too
+    large to draw on the host quickly).  Not bit-identical to
+    ``init_fields``; every storage type of one study receives the same
+    arrays."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(w.seed if seed is None else seed)
+    u = torch.rand((3,) + w.shape, generator=gen, device=device, dtype=torch.float64)
+    u.mul_(2.0).sub_(1.0).mul_(w.noise * w.u_ref)
+    y = torch.arange(w.ny, device=device, dtype=torch.float64) + 0.5
+    u[0] += (w.u_ref * (y / w.y_ref) ** (1.0 / 7.0))[None, :, None]
+    rho = torch.ones(w.shape, device=device, dtype=torch.float64)
+    return rho, u
+
+
+def random_populations(shape, seed: int, base, scale: float = 0.01):
+    """Arbitrary population fields f_q = base_q (1 + scale * xi), xi ~ U[-1, 1)
+    i.i.d., shape (19,) + shape; ``base`` (19 values) is supplied by the
+    caller."""
+    rng = np.random.default_rng(seed)
+    base = np.asarray(base, dtype=np.float64).reshape((19,) + (1,) * len(shape))
+    xi = rng.uniform(-1.0, 1.0, size=(19,) + tuple(shape))
+    return base * (1.0 + scale * xi)

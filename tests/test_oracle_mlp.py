@@ -1,0 +1,148 @@
+"""Pins of the oracle's learned closure (FP64 MLP forward/backward, blob).
+
+The network is a design choice of this project (the paper uses Smagorinsky
+and names other SGS models as future work), so the pins are mathematical:
+known values of GELU/softplus, the composition on a one-path network (fixes
+which index is input and which output), central finite differences of the
+loss (fixes the backward pass), and the blob layout written here
+independently with ``struct``.
+"""
+import math
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import ref
+
+NIN, NH1, NH2 = 9, 64, 64
+NP = NH1 * NIN + NH1 + NH2 * NH1 + NH2 + NH2 + 1
+
+
+def _bf16_bits(x):
+    """Round-to-nearest-even float32 -> bfloat16 bits (test-local)."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return b.astype(np.uint16)
+
+
+def _bf16_value(bits):
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _blob(W1, b1, W2, b2, w3, b3, mean, std, lo, hi, scale, h):
+    out = bytearray(b"LBMC")
+    out += struct.pack("<5I", 1, NIN, NH1, NH2, 0)
+    out += struct.pack("<36f", *mean, *std, *lo, *hi)
+    out += struct.pack("<4f", scale, h, 0, 0)
+    out += struct.pack("<132f", *b1, *b2, b3, 0, 0, 0)
+    out += _bf16_bits(np.concatenate([W1.ravel(), W2.ravel(), w3.ravel()])).tobytes()
+    assert len(out) == 10184
+    return bytes(out)
+
+
+def _flat(W1, b1, W2, b2, w3, b3):
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, [b3]])
+
+
+def test_gelu_softplus_values():
+    assert ref.gelu(0.0) == 0.0
+    assert ref.gelu(10.0) == pytest.approx(10.0, abs=1e-12)
+    assert abs(ref.gelu(-10.0)) < 1e-12
+    for x in np.linspace(-4, 4, 33):
+        exact = 0.5 * x * (1 + math.erf(x / math.sqrt(2)))  # GELU by definition
+        assert abs(ref.gelu(x) - exact) < 5e-4  # tanh form approximates it
+    assert ref.softplus(0.0) == pytest.approx(math.log(2.0), rel=1e-15)
+    assert ref.softplus(50.0) == pytest.approx(50.0, rel=1e-15)
+    assert ref.softplus(-50.0) == pytest.approx(math.exp(-50.0), rel=1e-12)
+    assert ref.softplus(800.0) == 800.0
+
+
+def test_one_path_network_fixes_indexing():
+    W1 = np.zeros((NH1, NIN)); b1 = np.zeros(NH1)
+    W2 = np.zeros((NH2, NH1)); b2 = np.zeros(NH2)
+    w3 = np.zeros(NH2)
+    a, bb, c, b3 = 0.7, -1.3, 2.1, 0.25
+    W1[3, 5] = a   # hidden unit 3 reads input 5
+    W2[7, 3] = bb  # hidden unit 7 of layer 2 reads unit 3 of layer 1
+    w3[7] = c
+    p = _flat(W1, b1, W2, b2, w3, b3)
+    Z = np.random.default_rng(1).normal(size=(20, NIN))
+    o = ref.mlp_apply(p, Z)
+    expect = b3 + c * np.array([ref.gelu(bb * ref.gelu(a * z[5])) for z in Z])
+    np.testing.assert_allclose(o, expect, rtol=1e-14, atol=1e-15)
+
+
+def test_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(2)
+    p = rng.normal(size=NP) * 0.3
+    Z = rng.normal(size=(16, NIN))
+    y = rng.uniform(0.1, 2.0, size=16)
+    loss, g = ref.mlp_loss_grad(p, Z, y)
+    o = ref.mlp_apply(p, Z)
+    assert loss == pytest.approx(np.mean((np.log1p(np.exp(o)) - y) ** 2), rel=1e-13)
+    idx = rng.choice(NP, size=120, replace=False)
+    idx = np.concatenate([idx, [0, NP - 1, NH1 * NIN, NH1 * NIN + NH1]])
+    def central(i, h):
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        return (ref.mlp_loss_grad(pp, Z, y)[0] - ref.mlp_loss_grad(pm, Z, y)[0]) / (2 * h)
+
+    for i in idx:
+        h = 1e-3 * max(1.0, abs(p[i]))
+        fd = (4 * central(i, h / 2) - central(i, h)) / 3  # Richardson, O(h^4)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+def test_blob_roundtrip_and_fallback():
+    rng = np.random.default_rng(3)
+    W1 = rng.normal(size=(NH1, NIN)) * 0.2; b1 = rng.normal(size=NH1) * 0.1
+    W2 = rng.normal(size=(NH2, NH1)) * 0.1; b2 = rng.normal(size=NH2) * 0.1
+    w3 = rng.normal(size=NH2) * 0.1; b3 = -1.0
+    mean = rng.normal(size=NIN).astype(np.float32)
+    std = rng.uniform(0.5, 2, size=NIN).astype(np.float32)
+    lo = np.full(NIN, -5.0); hi = np.full(NIN, 5.0)
+    blob = _blob(W1, b1, W2, b2, w3, b3, mean, std, lo, hi, 1e-4, 12.0)
+    m = ref.MLP(blob)
+    X = rng.uniform(-4, 4, size=(50, NIN))
+    X[0, 2] = 7.0  # out of range -> Smagorinsky value
+    smag = rng.uniform(0, 1e-4, 50)
+    nut, fb = m.predict(X, smag)
+    assert fb[0] == 1 and nut[0] == smag[0]
+    assert fb[1:].sum() == 0
+    # the same network from the BF16-rounded flat parameters
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    p = _flat(_bf16_value(_bf16_bits(W1)).reshape(W1.shape), f32(b1),
+              _bf16_value(_bf16_bits(W2)).reshape(W2.shape), f32(b2),
+              _bf16_value(_bf16_bits(w3)), float(np.float32(b3)))
+    Zs = (X[1:] - mean.astype(np.float64)) / std.astype(np.float64)
+    o = ref.mlp_apply(p, Zs)
+    np.testing.assert_allclose(nut[1:], float(np.float32(1e-4)) * np.log1p(np.exp(o)),
+                               rtol=1e-12)
+    with pytest.raises(ValueError):
+        ref.MLP(blob[:-2])
+    with pytest.raises(ValueError):
+        ref.MLP(b"XXXX" + blob[4:])
+
+
+def test_features_invariants():
+    """Rotation about the wall normal leaves all stress features unchanged;
+    tr P^2 = (Q^(1/2) / (rho c_s^2))^2."""
+    rng = np.random.default_rng(4)
+    blob = _blob(np.zeros((NH1, NIN)), np.zeros(NH1), np.zeros((NH2, NH1)), np.zeros(NH2),
+                 np.zeros(NH2), 0.0, np.zeros(NIN), np.ones(NIN), -np.ones(NIN),
+                 np.ones(NIN), 1.0, 12.0)
+    m = ref.MLP(blob)
+    A = rng.normal(size=(3, 3)) * 1e-3
+    Pineq = A + A.T
+    rho = 1.01
+    x = m.features(0.5005, rho, Pineq, 0.3, 0.2)
+    th = 0.7
+    R = np.array([[math.cos(th), 0, math.sin(th)], [0, 1, 0], [-math.sin(th), 0, math.cos(th)]])
+    x2 = m.features(0.5005, rho, R @ Pineq @ R.T, 0.3, 0.2)
+    np.testing.assert_allclose(x, x2, rtol=1e-12, atol=1e-18)
+    Qh = math.sqrt(np.sum(Pineq * Pineq))
+    assert x[5] == pytest.approx(Qh / (rho / 3), rel=1e-14)
+    assert x[1] == pytest.approx((Qh / (rho / 3)) ** 2, rel=1e-14)
+    assert x[0] == pytest.approx(np.trace(Pineq) / (rho / 3), rel=1e-14, abs=1e-18)
+    assert tuple(x[6:]) == (0.3, 0.2, 1.0)
