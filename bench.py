@@ -1,0 +1,193 @@
+"""Throughput of the fused LBM-LES-canopy step on one MI355X.
+
+A step is one lattice-Boltzmann time step of the whole hot path over the
+production canopy boundary layer (512x128x256 cells, FP32 storage,
+Smagorinsky closure, Lalic-Mihailovic LAD with h = 12, LAI 2, C_D = 0.15,
+bounce-back ground, free-slip top): one fused kernel launch that streams in
+place, applies the walls, computes the moments, the canopy drag, the eddy
+viscosity, the forced BGK collision, stores in place and accumulates the FP64
+impulse; every 10th step also accumulates the plane statistics, the last
+step writes the moments and the timed region ends with the FP64
+diagnostics reduction.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  value = cells * steps / time / 1e6 (MLUPS).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS and % of HBM roofline; low-precision+learned vs plain FP32 at "
+          "≤1% profile error")
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ELT = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+KERNEL_SOURCES = ("paper_2206_15454_amd/csrc/lbm_kernels.hip",
+                  "paper_2206_15454_amd/csrc/lbm_device.h")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, cells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(storage)
+    if not ent or ent.get("kernel_hash") != kernel_hash() or ent.get("cells") != cells:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def make_sim(w, storage, lbm, inputs):
+    lad = lbm.lad_lalic(*w.lad_lalic[:2], w.ny, lai=w.lad_lalic[2]) \
+        if w.lad_lalic is not None else inputs.lad_constant(w)
+    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    sim.set_canopy(w.cd, lad)
+    return sim
+
+
+def time_steps(sim, steps, warmup, torch):
+    """(total_ms, step_ms): events on the stream the kernels run on (torch's
+    current stream, handed to the library)."""
+    sim.stats_reset()
+    sim.stats_enable(10)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    d = sim.diag()  # FP64 reductions; synchronises
+    e2.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e2), e0.elapsed_time(e1), d
+
+
+def cpu_baseline(w, target_s=10.0):
+    """The FP64 oracle on a z-slab of the same workload (all host cores)."""
+    import numpy as np
+
+    from oracle import ref
+    from paper_2206_15454_amd import inputs
+
+    nz = max(1, min(w.nz, 16))
+    ws = inputs.scaled(w, w.nx, w.ny, nz)
+    h, ym, lai = w.lad_lalic
+    lad = ref.lad_lalic(h, ym, w.ny, lai=lai)
+    sim = ref.RefLBM(ws.nx, ws.ny, ws.nz, ws.tau0, ws.c_smag, ws.g, ws.bc_lo, ws.bc_hi)
+    sim.set_canopy(ws.cd, lad)
+    rho, u = inputs.init_fields(ws)
+    sim.init(rho, u)
+    t0 = time.perf_counter()
+    sim.step(2)
+    per = (time.perf_counter() - t0) / 2
+    steps = int(max(2, min(500, target_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    del np
+    return {"value": round(ws.n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": ref.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {ws.nx}x{ws.ny}x{ws.nz} z-slab of the same workload, "
+                      f"{steps} steps, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_ELT))
+    ap.add_argument("--variants", default="f64,f16s,bf16s",
+                    help="other storage types timed on the same workload ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the method here is a single-GPU kernel "
+              "(multi-GPU slab decomposition is not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2206_15454_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = inputs.C2
+    rho, u = inputs.init_fields(w)
+    rho_d = torch.from_numpy(rho).cuda()
+    u_d = torch.from_numpy(u).cuda()
+
+    def run(storage, steps, warmup):
+        sim = make_sim(w, storage, lbm, inputs)
+        sim.init(rho_d, u_d)
+        total, step_ms, d = time_steps(sim, steps, warmup, torch)
+        sim.close()
+        return total, step_ms, d
+
+    total_ms, step_ms, diag = run(args.storage, args.steps, args.warmup)
+    mlups = w.n * args.steps / (total_ms * 1e-3) / 1e6
+    per_launch_s = step_ms * 1e-3 / args.steps
+    algo_bytes = 2 * 19 * BYTES_PER_ELT[args.storage] * w.n
+    achieved = algo_bytes / per_launch_s / 1e9
+    traffic = measured_traffic(args.storage, w.n)
+
+    variants = {}
+    for st in [s for s in args.variants.split(",") if s and s != args.storage]:
+        k = max(50, args.steps // 4)
+        t_ms, s_ms, _ = run(st, k, 20)
+        b = 2 * 19 * BYTES_PER_ELT[st] * w.n
+        variants[st] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+                        "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz,
+                   "storage": args.storage, "closure": "smagorinsky", "canopy": "lalic h=12 LAI=2",
+                   "stats_every": 10},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "variants": variants,
+        "diag": {"mass": diag["mass"], "max_u": diag["max_u"], "t": diag["t"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) fused lattice-Boltzmann LES
+ * forest-canopy step.
+ *
+ * The method is that of Shao et al., "Near-wall approximations to speed up
+ * simulations for atmosphere boundary layers in the presence of forests using
+ * lattice Boltzmann method on GPU" (arXiv 2206.15454): D3Q19 BGK lattice
+ * Boltzmann with Guo forcing (Sec. 2.1), Smagorinsky eddy viscosity
+ * (Sec. 2.2), forest drag injected as a body force with a leaf-area-density
+ * profile (Sec. 2.3), in the per-step order of Algorithm 1 (Sec. 3).
+ *
+ * Conventions (every entry point):
+ *  - Lattice units: dx = dt = 1, c_s^2 = 1/3.  x is streamwise, y wall-normal,
+ *    z spanwise.  Cell (i,j,k) has centre height y_j = j + 1/2; the walls are
+ *    the planes y = 0 and y = ny.  x and z are periodic.
+ *  - Arrays are C order [component][z][y][x], x fastest.  Populations are
+ *    [19][z][y][x] in the direction order of lbm_lattice().
+ *  - Every call returns an lbm_status; no C++ exception crosses the ABI.
+ *    lbm_last_error() gives a message for the last failed call on a context.
+ *  - A context is used by one host thread at a time.  Work is enqueued on the
+ *    context's HIP stream; only lbm_moments, lbm_stats(READ) and lbm_get_f
+ *    synchronise that stream.
+ *  - "on_device" pointers are device pointers on the context's device;
+ *    otherwise host pointers.  The caller keeps ownership of every array it
+ *    passes; the library copies what it needs before returning.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,    /* invalid argument (value, size, NULL, blob shape) */
+    LBM_ENOMEM = 2,    /* device or host allocation failed, or dev_bytes too small */
+    LBM_EDEVICE = 3,   /* a HIP call failed; the message holds hipGetErrorString */
+    LBM_ESTATE = 4,    /* call not valid in the current state (e.g. step before init) */
+    LBM_EUNSTABLE = 5  /* non-finite moments or max |u| > 0.35 were found */
+} lbm_status;
+
+/* Population storage.  The "S" types store the shifted value f_i - w_i
+ * (w_i the lattice weight) so that the small deviations from rest keep their
+ * digits; F32 storage is shifted as well, F64 stores the same shifted value in
+ * double.  Arithmetic is FP64 for LBM_F64 and FP32 for the others.
+ * Rounding into storage is round-to-nearest-even. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
+
+/* Wall-normal (y) boundaries.  BOUNCEBACK is the halfway no-slip wall;
+ * FREESLIP is specular reflection (a symmetry plane); PERIODIC must be set
+ * on both ends or neither. */
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_FREESLIP = 2 } lbm_bc;
+
+typedef enum { LBM_CLOSURE_SMAG = 0, LBM_CLOSURE_MLP = 1 } lbm_closure;
+
+typedef struct lbm_params {
+    int32_t nx, ny, nz;  /* cells, each >= 1; nx*ny*nz < 2^31 */
+    int32_t storage;     /* lbm_storage */
+    double tau0;         /* molecular relaxation time, > 0.5 (nu0 = (tau0 - 1/2)/3) */
+    double c_smag;       /* Smagorinsky constant C_smag of Sec. 2.2 (= Cs^2), >= 0; 0 = off */
+    double g[3];         /* driving acceleration; force density rho*g (Sec. 4, Eq. Body_force) */
+    int32_t bc_ylo;      /* lbm_bc at y = 0  */
+    int32_t bc_yhi;      /* lbm_bc at y = ny */
+    void *stream;        /* hipStream_t to enqueue on; NULL = the null stream */
+} lbm_params;
+
+typedef struct lbm_diag {
+    double mass;         /* sum of rho over cells, FP64 */
+    double mom[3];       /* sum of rho u (force-corrected velocity), FP64 */
+    double impulse[3];   /* sum over all steps and cells of the body force F, FP64 */
+    double max_u;        /* max |u| over cells */
+    int64_t t;           /* steps done since lbm_init */
+    int64_t nonfinite;   /* cells whose rho, u or nu_t is not finite */
+    int64_t mlp_fallback;/* cells of the last step where the learned closure fell
+                            back to Smagorinsky (0 with the Smagorinsky closure) */
+} lbm_diag;
+
+/* D3Q19 direction table: rest; +x,-x,+y,-y,+z,-z; then the twelve edge
+ * vectors, each followed by its opposite (q odd and q+1 are opposite):
+ * (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+ * (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).  Weights 1/3, 1/18 (axis), 1/36
+ * (edge).  c: [19][3], w: [19] (either may be NULL).  Returns 19. */
+int32_t lbm_lattice(int32_t *c, double *w);
+
+/* Device bytes one context needs (populations, moments, partial sums).
+ * Returns 0 for invalid parameters. */
+size_t lbm_required_bytes(const lbm_params *p);
+
+/* Create a context on the current HIP device.  dev_buf == NULL: the library
+ * allocates; otherwise dev_buf is a caller-owned device buffer of dev_bytes
+ * >= lbm_required_bytes(p), 256-byte aligned, that must outlive the context.
+ * EINVAL for bad parameters (tau0 <= 0.5, a dimension < 1, periodic on one
+ * end only, unknown storage); ENOMEM if the buffer is too small or the
+ * allocation fails.  *out is NULL on failure. */
+lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out);
+
+/* Release the context (and its device memory if the library allocated it). */
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none; a static message for
+ * ctx == NULL). */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Change the stream later work is enqueued on. */
+lbm_status lbm_set_stream(lbm_ctx *ctx, void *stream);
+
+/* Forest canopy (Sec. 2.3, Eq. forestForce; Algorithm 1): drag acceleration
+ * a_d = -cd * lad[j] * |u*| * u*_x added to the x component of the body
+ * force in every cell of row j with lad[j] > 0, where u* is the velocity with
+ * the driving force only; vector_drag != 0 applies -cd*lad*|u*|*u* to all
+ * three components.  lad: host array of ny values (1/cell), ny must equal
+ * the context's ny.  Copied.  EINVAL for ny mismatch, NULL lad or a negative
+ * or non-finite value. */
+lbm_status lbm_set_canopy(lbm_ctx *ctx, double cd, const double *lad, int32_t ny,
+                          int32_t vector_drag);
+
+/* Eddy-viscosity closure.  LBM_CLOSURE_SMAG (blob ignored) restores Sec. 2.2.
+ * LBM_CLOSURE_MLP loads a learned closure blob (host memory, nbytes == 10184,
+ * format below) that replaces nu_t of Sec. 2.2 where its 9 input features lie
+ * inside the stored ranges, and falls back to the Smagorinsky value elsewhere.
+ * EINVAL for a bad magic, version, shape or size.
+ *
+ * Blob (little-endian):
+ *     0 char magic[4] "LBMC"; 4 u32 version 1; 8 u32 n_in 9, n_h1 64, n_h2 64, 0
+ *    24 f32 mean[9], std[9], lo[9], hi[9]
+ *   168 f32 out_scale s, canopy height h (cells), 0, 0
+ *   184 f32 b1[64], b2[64], b3, 0, 0, 0
+ *   712 bf16 W1[64][9], W2[64][64], w3[64]
+ * Network: z = (x - mean)/std; h1 = gelu(W1 z + b1); h2 = gelu(W2 h1 + b2);
+ * nu_t = s * softplus(w3.h2 + b3), gelu the tanh form.  Features, with
+ * P = Pi_neq/(rho/3) and n = e_y: tr P, tr P^2, tr P^3, n.P.n, n.P^2.n,
+ * sqrt(tr P^2), y_j/h, lad[j], 1.  Then tau = tau0 + 3 nu_t. */
+lbm_status lbm_set_closure(lbm_ctx *ctx, int32_t closure, const void *blob, size_t nbytes);
+
+/* Initial state: f = feq(rho, u) (Sec. 2.1, Eq. local_eq) taken as the
+ * post-collision populations at t = 0; resets t, the impulse and the
+ * statistics.  rho: [nz][ny][nx], u: [3][nz][ny][nx], FP64.  The moments
+ * read back before the first step are rho, u and nu_t = 0.  EINVAL for NULL. */
+lbm_status lbm_init(lbm_ctx *ctx, const double *rho, const double *u, int32_t on_device);
+
+/* Enqueue n >= 0 time steps, one fused kernel launch each (stream, walls,
+ * moments, canopy drag, closure, equilibrium + Guo forcing + BGK, in-place
+ * store), asynchronously.  The last step of the call also writes the moments
+ * (rho, u, nu_t) read by lbm_moments.  ESTATE before lbm_init or after an
+ * instability was reported. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Synchronise the stream, then copy the moments of the latest step (FP64,
+ * rho [N], u [3][N], nu_t [N]; any pointer may be NULL) and, if d != NULL,
+ * the FP64 diagnostics (deterministic two-pass reductions).  EUNSTABLE (with
+ * the outputs still written) if a non-finite value or max |u| > 0.35 is
+ * found; later steps then return ESTATE until lbm_init or lbm_set_f. */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *u, double *nu_t, int32_t on_device,
+                       lbm_diag *d);
+
+/* Plane statistics (time and x-z averages, Sec. 4 and Sec. 5.2).
+ * op 0 RESET: zero the sums.  op 1 ENABLE: sample after every step whose
+ * new t is a multiple of every (every = 0 disables).  op 2 READ: synchronise
+ * and write prof [ny][10] = means over samples and x-z of
+ * u, v, w, uu, vv, ww, uv, uw, vw, nu_t.  nsamples (may be NULL) receives
+ * the sample count. */
+lbm_status lbm_stats(lbm_ctx *ctx, int32_t op, int32_t every, double *prof, int64_t *nsamples);
+
+/* Overwrite the state with post-collision populations f [19][N] (FP64,
+ * rounded into the storage type); t is unchanged.  Clears an instability. */
+lbm_status lbm_set_f(lbm_ctx *ctx, const double *f, int32_t on_device);
+
+/* Read the current post-collision populations (decoded to FP64) [19][N];
+ * synchronises the stream. */
+lbm_status lbm_get_f(lbm_ctx *ctx, double *f, int32_t on_device);
+
+/* Leaf-area density of Eq. (af_theory) at cell centres y_j = j + 1/2:
+ * a(y) = afm * r^n * exp(n (1 - r)), r = (h - ym)/(h - y), n = 6 for y < ym,
+ * 1/2 for ym <= y < h, 0 for y >= h.  With lai > 0 the profile is rescaled so
+ * that sum_j a_j = lai (afm ignored).  Host only; out: ny values.  EINVAL for
+ * h <= 0, ym outside [0, h), ny < 1 or NULL out. */
+lbm_status lbm_lad_lalic(double h, double ym, double afm, double lai, int32_t ny, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,539 @@
+// lbm_api.hip -- host runtime and C ABI (include/lbm.h) of the fused
+// lattice-Boltzmann LES canopy step on MI355X (gfx950).
+//
+// One context owns one device allocation carved into: the in-place population
+// buffer (19 planes, stride padded), the moment planes of the latest step,
+// the canopy table, and the FP64 accumulators of the deterministic
+// reductions.  Every step is one kernel launch on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+#include "mlp_device.h"
+
+using namespace lbmx;
+
+struct lbm_ctx {
+    lbm_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    long long n = 0;     // cells
+    size_t elt = 0;      // bytes per stored population
+    size_t celt = 0;     // bytes per arithmetic value
+    long long qs = 0;    // population plane stride, elements
+    // launch geometry
+    int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
+    bool xcd_remap = true;
+    // device memory
+    void *base = nullptr;
+    bool owns = false;
+    size_t bytes = 0;
+    void *f = nullptr;
+    void *mom = nullptr;
+    double *lad = nullptr;
+    double *imp = nullptr;
+    double *stats = nullptr;
+    double *red = nullptr;   // diag partials [kRedBlocks*6] + final [16]
+    double *prof = nullptr;  // [ny*10]
+    void *mlp = nullptr;     // learned closure parameters
+    // host state
+    int64_t t = 0;
+    int parity = 0;
+    bool inited = false;
+    bool unstable = false;
+    int stats_every = 0;
+    int64_t stats_n = 0;
+    double cd = 0.0;
+    int vector_drag = 0;
+    int closure = LBM_CLOSURE_SMAG;
+    std::string err;
+};
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+constexpr size_t kAlign = 256;
+const char *kNoCtx = "lbm: NULL context";
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_bytes(int st) {
+    switch (st) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16S:
+    case LBM_BF16S: return 2;
+    default: return 0;
+    }
+}
+
+bool valid_params(const lbm_params *p, std::string *why) {
+    auto fail = [&](const char *m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!p) return fail("NULL params");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("every dimension must be >= 1");
+    if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) return fail("nx*ny*nz must be < 2^31");
+    if (storage_bytes(p->storage) == 0) return fail("unknown storage type");
+    if (!(p->tau0 > 0.5) || !std::isfinite(p->tau0)) return fail("tau0 must be > 0.5");
+    if (!(p->c_smag >= 0.0) || !std::isfinite(p->c_smag)) return fail("c_smag must be >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->g[a])) return fail("g must be finite");
+    if (p->bc_ylo < 0 || p->bc_ylo > 2 || p->bc_yhi < 0 || p->bc_yhi > 2)
+        return fail("unknown boundary condition");
+    if ((p->bc_ylo == LBM_BC_PERIODIC) != (p->bc_yhi == LBM_BC_PERIODIC))
+        return fail("periodic y must be set on both ends");
+    return true;
+}
+
+// launch geometry: tiles of BX x 1 x BZ cells (BX*BZ = 256), one row each
+void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
+    int BX = 256;
+    if (const char *e = std::getenv("LBMX_BX")) {
+        int v = std::atoi(e);
+        if (v == 64 || v == 128 || v == 256) BX = v;
+    }
+    while (BX > 64 && BX / 2 >= p->nx) BX /= 2;
+    *bx = BX;
+    *bz = 256 / BX;
+    *nbx = (p->nx + BX - 1) / BX;
+    *nbz = (p->nz + *bz - 1) / *bz;
+}
+
+// population plane stride: rounded to 256 B plus a pad that staggers the 19
+// plane starts across HBM channels
+long long plane_stride(long long n, size_t elt) {
+    long long per = (long long)(kAlign / elt);
+    long long qs = (n + per - 1) / per * per;
+    long long pad_bytes = 0;
+    if (const char *e = std::getenv("LBMX_QPAD")) pad_bytes = std::atoll(e);
+    else pad_bytes = 4096 + 256;
+    qs += (long long)(align_up((size_t)pad_bytes, kAlign) / elt);
+    return qs;
+}
+
+struct Layout {
+    size_t f, mom, lad, imp, stats, red, prof, mlp, total;
+};
+
+Layout layout(const lbm_params *p) {
+    Layout L{};
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    const size_t elt = storage_bytes(p->storage);
+    const size_t celt = p->storage == LBM_F64 ? 8 : 4;
+    int bx, bz, nbx, nbz;
+    geometry(p, &bx, &bz, &nbx, &nbz);
+    const long long ntiles = (long long)nbx * nbz * p->ny;
+    const long long qs = plane_stride(n, elt);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, kAlign);
+        return at;
+    };
+    L.f = take((size_t)NQ * qs * elt);
+    L.mom = take((size_t)5 * n * celt);
+    L.lad = take((size_t)p->ny * 8);
+    L.imp = take((size_t)ntiles * 3 * 8);
+    L.stats = take((size_t)p->ny * nbx * nbz * 10 * 8);
+    L.red = take((size_t)(kRedBlocks * 6 + 16) * 8);
+    L.prof = take((size_t)p->ny * 10 * 8);
+    L.mlp = take(kMlpDeviceBytes);
+    L.total = off;
+    return L;
+}
+
+lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
+    return fail(c, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call, what)                          \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+lbm_status reset_accumulators(lbm_ctx *c) {
+    HIPCHK(c, launch_fill(c->imp, 0.0, (size_t)c->ntiles * 3, c->stream), "clear impulse");
+    HIPCHK(c, launch_fill(c->stats, 0.0, (size_t)c->p.ny * c->tpp * 10, c->stream),
+           "clear statistics");
+    c->stats_n = 0;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_lattice(int32_t *c, double *w) {
+    for (int q = 0; q < NQ; ++q) {
+        if (c) {
+            c[3 * q + 0] = CX[q];
+            c[3 * q + 1] = CY[q];
+            c[3 * q + 2] = CZ[q];
+        }
+        if (w) w[q] = weight(q);
+    }
+    return NQ;
+}
+
+size_t lbm_required_bytes(const lbm_params *p) {
+    if (!valid_params(p, nullptr)) return 0;
+    return layout(p).total;
+}
+
+lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(p, &why)) return LBM_EINVAL;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(p->stream);
+    c->n = (long long)p->nx * p->ny * p->nz;
+    c->elt = storage_bytes(p->storage);
+    c->celt = p->storage == LBM_F64 ? 8 : 4;
+    c->qs = plane_stride(c->n, c->elt);
+    geometry(p, &c->bx, &c->bz, &c->nbx, &c->nbz);
+    c->tpp = c->nbx * c->nbz;
+    c->ntiles = c->tpp * p->ny;
+    if (const char *e = std::getenv("LBMX_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    const Layout L = layout(p);
+    c->bytes = L.total;
+    if (dev_buf) {
+        if (dev_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) != 0) {
+            delete c;
+            return LBM_ENOMEM;
+        }
+        c->base = dev_buf;
+        c->owns = false;
+    } else {
+        if (hipMalloc(&c->base, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            return LBM_ENOMEM;
+        }
+        c->owns = true;
+    }
+    char *b = static_cast<char *>(c->base);
+    c->f = b + L.f;
+    c->mom = b + L.mom;
+    c->lad = reinterpret_cast<double *>(b + L.lad);
+    c->imp = reinterpret_cast<double *>(b + L.imp);
+    c->stats = reinterpret_cast<double *>(b + L.stats);
+    c->red = reinterpret_cast<double *>(b + L.red);
+    c->prof = reinterpret_cast<double *>(b + L.prof);
+    c->mlp = b + L.mlp;
+    if (launch_fill(c->lad, 0.0, (size_t)p->ny, c->stream) != hipSuccess ||
+        reset_accumulators(c) != LBM_OK) {
+        if (c->owns) (void)hipFree(c->base);
+        delete c;
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    if (c->owns && c->base) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->base);
+    }
+    delete c;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : kNoCtx; }
+
+lbm_status lbm_set_stream(lbm_ctx *c, void *stream) {
+    if (!c) return LBM_EINVAL;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->p.stream = stream;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_canopy(lbm_ctx *c, double cd, const double *lad, int32_t ny,
+                          int32_t vector_drag) {
+    if (!c) return LBM_EINVAL;
+    if (!lad) return fail(c, LBM_EINVAL, "lbm_set_canopy: NULL lad");
+    if (ny != c->p.ny) return fail(c, LBM_EINVAL, "lbm_set_canopy: lad length must equal ny");
+    if (!std::isfinite(cd)) return fail(c, LBM_EINVAL, "lbm_set_canopy: cd must be finite");
+    for (int j = 0; j < ny; ++j)
+        if (!(lad[j] >= 0.0) || !std::isfinite(lad[j]))
+            return fail(c, LBM_EINVAL, "lbm_set_canopy: lad values must be finite and >= 0");
+    HIPCHK(c, hipMemcpyAsync(c->lad, lad, (size_t)ny * 8, hipMemcpyHostToDevice, c->stream),
+           "lbm_set_canopy: copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_canopy: sync");
+    c->cd = cd;
+    c->vector_drag = vector_drag ? 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_closure(lbm_ctx *c, int32_t closure, const void *blob, size_t nbytes) {
+    if (!c) return LBM_EINVAL;
+    if (closure == LBM_CLOSURE_SMAG) {
+        c->closure = LBM_CLOSURE_SMAG;
+        return LBM_OK;
+    }
+    if (closure != LBM_CLOSURE_MLP) return fail(c, LBM_EINVAL, "lbm_set_closure: unknown closure");
+    std::vector<unsigned char> dev(kMlpDeviceBytes);
+    std::string why;
+    if (!mlp_pack_blob(blob, nbytes, dev.data(), &why))
+        return fail(c, LBM_EINVAL, "lbm_set_closure: " + why);
+    HIPCHK(c, hipMemcpyAsync(c->mlp, dev.data(), dev.size(), hipMemcpyHostToDevice, c->stream),
+           "lbm_set_closure: copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_closure: sync");
+    c->closure = LBM_CLOSURE_MLP;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx *c, const double *rho, const double *u, int32_t on_device) {
+    if (!c) return LBM_EINVAL;
+    if (!rho || !u) return fail(c, LBM_EINVAL, "lbm_init: NULL rho or u");
+    const long long n = c->n;
+    const double *drho = rho, *du = u;
+    double *tmp = nullptr;
+    if (!on_device) {
+        HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&tmp), (size_t)4 * n * 8, c->stream),
+               "lbm_init: staging");
+        HIPCHK(c, hipMemcpyAsync(tmp, rho, (size_t)n * 8, hipMemcpyHostToDevice, c->stream),
+               "lbm_init: copy rho");
+        HIPCHK(c, hipMemcpyAsync(tmp + n, u, (size_t)3 * n * 8, hipMemcpyHostToDevice, c->stream),
+               "lbm_init: copy u");
+        drho = tmp;
+        du = tmp + n;
+    }
+    HIPCHK(c, launch_init(c->p.storage, c->f, c->qs, c->mom, drho, du, (int)n, c->stream),
+           "lbm_init: kernel");
+    if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_init: free staging");
+    lbm_status s = reset_accumulators(c);
+    if (s != LBM_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_init: sync");
+    c->t = 0;
+    c->parity = 0;
+    c->inited = true;
+    c->unstable = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "lbm_step: n must be >= 0");
+    if (!c->inited) return fail(c, LBM_ESTATE, "lbm_step: call lbm_init first");
+    if (c->unstable) return fail(c, LBM_ESTATE, "lbm_step: the state is unstable; re-initialise");
+    StepArgs a{};
+    a.f = c->f;
+    a.qs = c->qs;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nz = c->p.nz;
+    a.nbx = c->nbx;
+    a.nbz = c->nbz;
+    a.ntiles = c->ntiles;
+    a.bc_lo = c->p.bc_ylo;
+    a.bc_hi = c->p.bc_yhi;
+    a.tau0 = c->p.tau0;
+    a.ksmag = 18.0 * std::sqrt(2.0) * c->p.c_smag;
+    for (int d = 0; d < 3; ++d) a.g[d] = c->p.g[d];
+    a.cd = c->cd;
+    a.lad = c->lad;
+    a.mom = c->mom;
+    a.imp = c->imp;
+    a.stats = c->stats;
+    a.mlp = c->mlp;
+    int base_flags = FLAG_IMPULSE;
+    if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
+    if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
+    if (c->closure == LBM_CLOSURE_MLP) base_flags |= FLAG_MLP;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        a.parity = c->parity;
+        a.flags = base_flags;
+        if (s == nsteps - 1) a.flags |= FLAG_MOMENTS;
+        const bool sample = c->stats_every > 0 && (c->t + 1) % c->stats_every == 0;
+        if (sample) a.flags |= FLAG_STATS;
+        hipError_t e = (c->closure == LBM_CLOSURE_MLP)
+                           ? launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->stream)
+                           : launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "lbm_step: launch");
+        c->parity ^= 1;
+        c->t += 1;
+        if (sample) c->stats_n += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, double *nut, int32_t on_device,
+                       lbm_diag *d) {
+    if (!c) return LBM_EINVAL;
+    if (!c->inited) return fail(c, LBM_ESTATE, "lbm_moments: call lbm_init first");
+    const long long n = c->n;
+    if (rho || u || nut) {
+        if (on_device) {
+            HIPCHK(c, launch_moments_out(c->p.storage, c->mom, rho, u, nut, (int)n, c->stream),
+                   "lbm_moments: convert");
+        } else if (c->celt == 8) {
+            const double *m = static_cast<const double *>(c->mom);
+            if (rho) HIPCHK(c, hipMemcpyAsync(rho, m, n * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+            if (u) HIPCHK(c, hipMemcpyAsync(u, m + n, 3 * n * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+            if (nut) HIPCHK(c, hipMemcpyAsync(nut, m + 4 * n, n * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+        } else {
+            std::vector<float> h((size_t)5 * n);
+            HIPCHK(c, hipMemcpyAsync(h.data(), c->mom, (size_t)5 * n * 4, hipMemcpyDeviceToHost,
+                                     c->stream), "lbm_moments: copy");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_moments: sync");
+            for (long long x = 0; x < n; ++x) {
+                if (rho) rho[x] = h[x];
+                if (u) {
+                    u[x] = h[n + x];
+                    u[n + x] = h[2 * n + x];
+                    u[2 * n + x] = h[3 * n + x];
+                }
+                if (nut) nut[x] = h[4 * n + x];
+            }
+        }
+    }
+    double out[9] = {0};
+    HIPCHK(c, launch_diag(c->p.storage, c->mom, (int)n, c->imp, c->ntiles, c->red, kRedBlocks,
+                          c->red + kRedBlocks * 6, c->stream), "lbm_moments: reduce");
+    HIPCHK(c, hipMemcpyAsync(out, c->red + kRedBlocks * 6, sizeof(out), hipMemcpyDeviceToHost,
+                             c->stream), "lbm_moments: copy diag");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_moments: sync");
+    int64_t fb = 0;
+    if (c->closure == LBM_CLOSURE_MLP) {
+        lbm_status s = mlp_fallback_count(c->mlp, &fb, c->stream);
+        if (s != LBM_OK) return fail(c, s, "lbm_moments: fallback count");
+    }
+    if (d) {
+        d->mass = out[0];
+        d->mom[0] = out[1];
+        d->mom[1] = out[2];
+        d->mom[2] = out[3];
+        d->impulse[0] = out[4];
+        d->impulse[1] = out[5];
+        d->impulse[2] = out[6];
+        d->max_u = out[7];
+        d->t = c->t;
+        d->nonfinite = (int64_t)out[8];
+        d->mlp_fallback = fb;
+    }
+    if (out[8] > 0 || out[7] > 0.35 || !std::isfinite(out[7])) {
+        c->unstable = true;
+        return fail(c, LBM_EUNSTABLE, "lbm_moments: non-finite values or max |u| > 0.35");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_stats(lbm_ctx *c, int32_t op, int32_t every, double *prof, int64_t *nsamples) {
+    if (!c) return LBM_EINVAL;
+    if (op == 0) {
+        lbm_status s = reset_accumulators(c);
+        if (s != LBM_OK) return s;
+    } else if (op == 1) {
+        if (every < 0) return fail(c, LBM_EINVAL, "lbm_stats: every must be >= 0");
+        c->stats_every = every;
+    } else if (op == 2) {
+        if (!prof) return fail(c, LBM_EINVAL, "lbm_stats: NULL prof");
+        std::vector<double> h((size_t)c->p.ny * 10);
+        HIPCHK(c, launch_stats_read(c->stats, c->p.ny, c->tpp, c->prof, c->stream),
+               "lbm_stats: reduce");
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->prof, h.size() * 8, hipMemcpyDeviceToHost,
+                                 c->stream), "lbm_stats: copy");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_stats: sync");
+        const double denom = (double)c->stats_n * c->p.nx * c->p.nz;
+        for (size_t k = 0; k < h.size(); ++k) prof[k] = c->stats_n ? h[k] / denom : 0.0;
+    } else {
+        return fail(c, LBM_EINVAL, "lbm_stats: op must be 0 (reset), 1 (enable) or 2 (read)");
+    }
+    if (nsamples) *nsamples = c->stats_n;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_f(lbm_ctx *c, const double *fin, int32_t on_device) {
+    if (!c) return LBM_EINVAL;
+    if (!fin) return fail(c, LBM_EINVAL, "lbm_set_f: NULL f");
+    const long long n = c->n;
+    const double *src = fin;
+    double *tmp = nullptr;
+    if (!on_device) {
+        HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&tmp), (size_t)NQ * n * 8, c->stream),
+               "lbm_set_f: staging");
+        HIPCHK(c, hipMemcpyAsync(tmp, fin, (size_t)NQ * n * 8, hipMemcpyHostToDevice, c->stream),
+               "lbm_set_f: copy");
+        src = tmp;
+    }
+    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, (int)n, c->stream), "lbm_set_f: kernel");
+    if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_set_f: free staging");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_f: sync");
+    c->parity = 0;
+    c->inited = true;
+    c->unstable = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_f(lbm_ctx *c, double *fout, int32_t on_device) {
+    if (!c) return LBM_EINVAL;
+    if (!fout) return fail(c, LBM_EINVAL, "lbm_get_f: NULL f");
+    if (!c->inited) return fail(c, LBM_ESTATE, "lbm_get_f: call lbm_init first");
+    const long long n = c->n;
+    double *dst = fout;
+    double *tmp = nullptr;
+    if (!on_device) {
+        HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&tmp), (size_t)NQ * n * 8, c->stream),
+               "lbm_get_f: staging");
+        dst = tmp;
+    }
+    HIPCHK(c, launch_get_f(c->p.storage, c->f, c->qs, dst, c->p.nx, c->p.ny, c->p.nz, c->parity,
+                           c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_get_f: kernel");
+    if (tmp) {
+        HIPCHK(c, hipMemcpyAsync(fout, tmp, (size_t)NQ * n * 8, hipMemcpyDeviceToHost, c->stream),
+               "lbm_get_f: copy");
+        HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_get_f: free staging");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_get_f: sync");
+    return LBM_OK;
+}
+
+lbm_status lbm_lad_lalic(double h, double ym, double afm, double lai, int32_t ny, double *out) {
+    if (!out || ny < 1 || !(h > 0.0) || !(ym >= 0.0) || !(ym < h) || !std::isfinite(h))
+        return LBM_EINVAL;
+    double sum = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        const double y = j + 0.5;
+        double a = 0.0;
+        if (y < h) {
+            const double nexp = y < ym ? 6.0 : 0.5;
+            const double r = (h - ym) / (h - y);
+            a = std::exp(nexp * (std::log(r) + 1.0 - r));
+        }
+        out[j] = a;
+        sum += a;
+    }
+    double scale = afm;
+    if (lai > 0.0) {
+        if (!(sum > 0.0)) return LBM_EINVAL;
+        scale = lai / sum;
+    }
+    for (int j = 0; j < ny; ++j) out[j] *= scale;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// lbm_device.h -- internal definitions shared by the HIP translation units of
+// the fused lattice-Boltzmann LES canopy step (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace lbmx {
+
+constexpr int NQ = 19;
+
+// D3Q19 in the interface direction order: rest; +x,-x,+y,-y,+z,-z; edge
+// vectors in opposite pairs (q odd, q+1).  Weights 1/3, 1/18, 1/36.
+constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+
+// direction with the y component of c_q reversed (specular reflection off a
+// y = const plane)
+constexpr int mir(int q) {
+    for (int p = 0; p < NQ; ++p)
+        if (CX[p] == CX[q] && CY[p] == -CY[q] && CZ[p] == CZ[q]) return p;
+    return -1;
+}
+
+constexpr double weight(int q) {
+    return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2 };
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+
+// step flags
+enum : int {
+    FLAG_MOMENTS = 1,      // write rho, u, nu_t of this collision
+    FLAG_STATS = 2,        // accumulate the plane statistics of this step
+    FLAG_VECTOR_DRAG = 4,  // canopy drag on all three components
+    FLAG_XCD_REMAP = 8,    // keep consecutive tiles on one XCD
+    FLAG_IMPULSE = 16,     // accumulate the body-force impulse
+    FLAG_MLP = 32          // learned closure
+};
+
+// Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
+// non-temporal (streaming) cache policy; every population is touched once
+// per step, so there is no reuse for the caches to keep.
+#ifndef LBMX_NT_LOAD
+#define LBMX_NT_LOAD 0
+#endif
+#ifndef LBMX_NT_STORE
+#define LBMX_NT_STORE 1
+#endif
+template <class T> __device__ __forceinline__ T pop_ld(const T *p) {
+#if LBMX_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <class T> __device__ __forceinline__ void pop_st(T *p, T v) {
+#if LBMX_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Storage codecs: T is the element type in HBM, C the arithmetic type.
+// Stored values are shifted populations f_q - w_q.
+template <int ST> struct Codec;
+template <> struct Codec<ST_F64> {
+    using T = double;
+    using C = double;
+    static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
+    static __device__ __forceinline__ void st(T *p, C v) { pop_st(p, v); }
+};
+template <> struct Codec<ST_F32> {
+    using T = float;
+    using C = float;
+    static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
+    static __device__ __forceinline__ void st(T *p, C v) { pop_st(p, v); }
+};
+template <> struct Codec<ST_F16S> {
+    using T = _Float16;
+    using C = float;
+    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
+    static __device__ __forceinline__ void st(T *p, C v) {
+        pop_st(p, (_Float16)v);  // round to nearest even
+    }
+};
+template <> struct Codec<ST_BF16S> {
+    using T = __bf16;
+    using C = float;
+    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
+    static __device__ __forceinline__ void st(T *p, C v) {
+        pop_st(p, (__bf16)v);  // v_cvt_pk_bf16_f32, nearest even
+    }
+};
+
+// Arguments of one fused step launch (passed by value as kernel arguments).
+struct StepArgs {
+    void *f;          // population buffer, q-plane stride qs elements
+    long long qs;
+    int nx, ny, nz;
+    int nbx, nbz;     // tiles per row (x) and per column (z); tile = BX x 1 x BZ cells
+    int ntiles;       // nbx * nbz * ny = grid size
+    int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
+    int bc_lo, bc_hi;
+    int flags;
+    double tau0;      // molecular relaxation time
+    double ksmag;     // 18 sqrt(2) C_smag
+    double g[3];      // driving acceleration
+    double cd;        // canopy drag coefficient
+    const double *lad;  // [ny]
+    void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
+    double *imp;      // [ntiles][3] body-force impulse accumulators
+    double *stats;    // [ny][nbx*nbz][10] statistics accumulators
+    const void *mlp;  // learned closure parameters on the device
+};
+
+// compile-time loop
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Blocks are handed to the 8 XCDs round robin (block b runs on XCD b % 8).
+// Remap so that XCD x processes one contiguous range of tiles: tiles that
+// share cache lines (x neighbours) then meet in the same L2.  A bijection
+// of [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, local = b >> 3;
+    return x * q + (x < r ? x : r) + local;
+}
+
+// Launchers (defined in lbm_kernels.hip).
+hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s);
+hipError_t launch_init(int storage, void *f, long long qs, void *mom, const double *rho,
+                       const double *u, int n, hipStream_t s);
+hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
+                        hipStream_t s);
+hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
+                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);
+hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
+                              double *nut, int n, hipStream_t s);
+hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, int nimp,
+                       double *partial, int nblocks, double *out, hipStream_t s);
+hipError_t launch_stats_read(const double *stats, int ny, int tpp, double *prof,
+                             hipStream_t s);
+hipError_t launch_fill(double *p, double v, size_t n, hipStream_t s);
+
+}  // namespace lbmx

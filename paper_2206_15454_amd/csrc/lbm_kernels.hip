@@ -1,0 +1,521 @@
+// lbm_kernels.hip -- gfx950 kernels of the fused lattice-Boltzmann LES canopy
+// step and its auxiliary passes (init, state import/export, moments,
+// deterministic FP64 reductions, plane statistics).
+//
+// Method (Shao et al., arXiv 2206.15454): D3Q19 BGK with Guo forcing
+// (Sec. 2.1, Eqs. lbe, bgk, local_eq, bodyforce, density, momentum, tensor),
+// Smagorinsky eddy viscosity (Sec. 2.2), forest drag as a body force
+// (Sec. 2.3, Eq. forestForce), per-step order of Algorithm 1 (Sec. 3):
+// stream, velocity, forest force, corrected velocity, collide with the force.
+//
+// Storage scheme (this implementation, not the paper's double population):
+// one population buffer updated in place with the AA access pattern.
+//   local step  (parity 1): cell x reads slot q of x (incoming f_q) and writes
+//                           f*_q to slot opp(q) of x;
+//   neighbour step (parity 0): cell x reads slot opp(q) of x - c_q (which holds
+//                           f*_q of the upstream cell) and writes f*_q to slot
+//                           q of x + c_q.
+// In both, a cell reads and writes the same 19 slots, so no two cells touch a
+// common slot and the update is race free.  Walls are folded into the slot
+// map: halfway bounce-back keeps a population in its own cell with the
+// opposite direction; free slip moves it tangentially within the wall row
+// with the y component reversed.
+#include "lbm_device.h"
+
+namespace lbmx {
+
+namespace {
+
+template <class C> __device__ __forceinline__ C wave_sum(C v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of K values (256 threads = 4 waves): wave
+// butterflies, then a fixed-order sum of the 4 wave results in FP64.
+// Thread c < K adds the block total of value c into acc[c].
+template <int K, class C>
+__device__ __forceinline__ void block_accumulate(const C (&v)[K], double *acc, double *sh) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        C s = wave_sum(v[c]);
+        if (lane == 0) sh[wave * K + c] = (double)s;
+    }
+    __syncthreads();
+    if (tid < K) {
+        double t = sh[tid] + sh[K + tid];
+        t += sh[2 * K + tid];
+        t += sh[3 * K + tid];
+        acc[tid] += t;
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    T *__restrict__ f = static_cast<T *>(a.f);
+
+    int tile = blockIdx.x;
+    if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
+    const int bx = tile % a.nbx;
+    const int rest = tile / a.nbx;
+    const int bz = rest % a.nbz;
+    const int j = rest / a.nbz;  // the whole block lies in row j
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int i = bx * (int)blockDim.x + (int)threadIdx.x;
+    const int k = bz * (int)blockDim.y + (int)threadIdx.y;
+    const bool active = (i < nx) && (k < nz);
+    const int ic = i < nx ? i : nx - 1;  // clamped: inactive lanes load valid memory
+    const int kc = k < nz ? k : nz - 1;
+
+    // neighbour coordinates with periodic wrap (y wraps only if periodic;
+    // otherwise out-of-range rows go through the wall branches)
+    const int xs[3] = {ic == 0 ? nx - 1 : ic - 1, ic, ic == nx - 1 ? 0 : ic + 1};
+    const int zs[3] = {kc == 0 ? nz - 1 : kc - 1, kc, kc == nz - 1 ? 0 : kc + 1};
+    const int ys[3] = {j == 0 ? ny - 1 : j - 1, j, j == ny - 1 ? 0 : j + 1};
+    auto cell = [&](int dx, int dy, int dz) -> int {
+        return (zs[dz + 1] * ny + ys[dy + 1]) * nx + xs[dx + 1];
+    };
+    const int self = cell(0, 0, 0);
+    const long long qs = a.qs;
+
+    // ---- a1/a2: stream in (AA slot map with walls), decode ----------------
+    C v[NQ];
+    if (a.parity) {
+        static_for<NQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            v[q] = CD::ld(f + q * qs + self);
+        });
+    } else {
+        static_for<NQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+            const int js = j - cy;
+            if (cy != 0 && (js < 0 || js >= ny) &&
+                (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
+                if ((js < 0 ? a.bc_lo : a.bc_hi) == BC_BOUNCEBACK)
+                    v[q] = CD::ld(f + q * qs + self);  // left this cell towards the wall
+                else  // free slip: left the wall row upstream, moving towards the wall
+                    v[q] = CD::ld(f + opp(mir(q)) * qs + cell(-cx, 0, -cz));
+            } else {
+                v[q] = CD::ld(f + opp(q) * qs + cell(-cx, -cy, -cz));
+            }
+        });
+    }
+
+    // ---- a3: moments from the shifted values (no cancellation) ------------
+    // drho = sum f~, j = sum f~ c, P = sum f~ c c  (f = f~ + w; sum w c c = I/3)
+    C drho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+    static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+        const C x = v[q];
+        drho += x;
+        if (cx) jx += cx > 0 ? x : -x;
+        if (cy) jy += cy > 0 ? x : -x;
+        if (cz) jz += cz > 0 ? x : -x;
+        if (cx) pxx += x;
+        if (cy) pyy += x;
+        if (cz) pzz += x;
+        if (cx && cy) pxy += (cx * cy > 0) ? x : -x;
+        if (cx && cz) pxz += (cx * cz > 0) ? x : -x;
+        if (cy && cz) pyz += (cy * cz > 0) ? x : -x;
+    });
+    const C rho = C(1) + drho;
+    const C irho = C(1) / rho;
+
+    // ---- a4: velocity with the driving force, canopy drag, corrected u ----
+    const C gx = (C)a.g[0], gy = (C)a.g[1], gz = (C)a.g[2];
+    C ux = (jx + C(0.5) * rho * gx) * irho;
+    C uy = (jy + C(0.5) * rho * gy) * irho;
+    C uz = (jz + C(0.5) * rho * gz) * irho;
+    C ax = gx, ay = gy, az = gz;  // total acceleration
+    const C lad = (C)a.lad[j];
+    if (lad > C(0)) {  // uniform per block: the block is one row
+        const C speed = sqrt(ux * ux + uy * uy + uz * uz);
+        const C kd = -(C)a.cd * lad * speed;  // drag acceleration per unit velocity
+        const C adx = kd * ux;
+        ax += adx;
+        if (a.flags & FLAG_VECTOR_DRAG) {
+            const C ady = kd * uy, adz = kd * uz;
+            ay += ady;
+            az += adz;
+            uy += C(0.5) * ady;
+            uz += C(0.5) * adz;
+        }
+        ux += C(0.5) * adx;
+    }
+    const C Fx = rho * ax, Fy = rho * ay, Fz = rho * az;
+
+    // ---- a5: Smagorinsky: Pi_neq = P - drho/3 I - rho u u -----------------
+    const C third = C(1) / C(3);
+    const C nxx = pxx - drho * third - rho * ux * ux;
+    const C nyy = pyy - drho * third - rho * uy * uy;
+    const C nzz = pzz - drho * third - rho * uz * uz;
+    const C nxy = pxy - rho * ux * uy;
+    const C nxz = pxz - rho * ux * uz;
+    const C nyz = pyz - rho * uy * uz;
+    const C Qh = sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
+                      C(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
+    const C tau0 = (C)a.tau0;
+    // tau = (tau0 + sqrt(tau0^2 + X))/2, X = 18 sqrt2 C Q^(1/2)/rho, written
+    // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
+    const C X = (C)a.ksmag * Qh * irho;
+    const C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
+    const C tau = tau0 + C(3) * nut;
+    const C itau = C(1) / tau;
+
+    // ---- a6: equilibrium + Guo forcing + BGK (shifted) ----------------------
+    const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
+    const C uF = ux * Fx + uy * Fy + uz * Fz;
+    const C pref = C(1) - C(0.5) * itau;
+    static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+        constexpr C w = (C)weight(q);
+        C cu = 0, cF = 0;
+        if (cx) { cu += cx > 0 ? ux : -ux; cF += cx > 0 ? Fx : -Fx; }
+        if (cy) { cu += cy > 0 ? uy : -uy; cF += cy > 0 ? Fy : -Fy; }
+        if (cz) { cu += cz > 0 ? uz : -uz; cF += cz > 0 ? Fz : -Fz; }
+        const C feqs = w * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq15));
+        const C Fq = pref * w * (C(3) * (cF - uF) + C(9) * cu * cF);
+        v[q] = v[q] + (feqs - v[q]) * itau + Fq;
+    });
+
+    // ---- a7: store in place --------------------------------------------------
+    if (active) {
+        if (a.parity) {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                CD::st(f + opp(q) * qs + self, v[q]);
+            });
+        } else {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+                const int jt = j + cy;
+                if (cy != 0 && (jt < 0 || jt >= ny) &&
+                    (jt < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
+                    if ((jt < 0 ? a.bc_lo : a.bc_hi) == BC_BOUNCEBACK)
+                        CD::st(f + opp(q) * qs + self, v[q]);
+                    else
+                        CD::st(f + mir(q) * qs + cell(cx, 0, cz), v[q]);
+                } else {
+                    CD::st(f + q * qs + cell(cx, cy, cz), v[q]);
+                }
+            });
+        }
+    }
+
+    // ---- a8: moments of this collision -------------------------------------
+    if ((a.flags & FLAG_MOMENTS) && active) {
+        C *m = static_cast<C *>(a.mom);
+        const long long n = (long long)nx * ny * nz;
+        m[self] = rho;
+        m[n + self] = ux;
+        m[2 * n + self] = uy;
+        m[3 * n + self] = uz;
+        m[4 * n + self] = nut;
+    }
+
+    // ---- body-force impulse and plane statistics (FP64 accumulators) ------
+    __shared__ double sh[4 * 10];
+    if (a.flags & FLAG_IMPULSE) {
+        const C z = 0;
+        const C fv[3] = {active ? Fx : z, active ? Fy : z, active ? Fz : z};
+        block_accumulate<3>(fv, a.imp + 3 * (long long)tile, sh);
+    }
+    if (a.flags & FLAG_STATS) {
+        if (a.flags & FLAG_IMPULSE) __syncthreads();  // sh reused
+        const C m = active ? C(1) : C(0);
+        const C sv[10] = {m * ux,      m * uy,      m * uz,      m * ux * ux, m * uy * uy,
+                          m * uz * uz, m * ux * uy, m * ux * uz, m * uy * uz, m * nut};
+        const long long slot = ((long long)j * (a.nbx * a.nbz) + bz * a.nbx + bx) * 10;
+        block_accumulate<10>(sv, a.stats + slot, sh);
+    }
+}
+
+// f = feq(rho, u) as post-collision populations, stored shifted in the
+// layout a neighbour step reads (slot opp(q) of the own cell).
+template <int ST>
+__global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, void *mom,
+                                                   const double *rho, const double *u, int n) {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    T *f = static_cast<T *>(fp);
+    const double r = rho[x], ux = u[x], uy = u[n + x], uz = u[2 * (long long)n + x];
+    const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
+    static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
+        const double w = weight(q);
+        const double fs = w * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - usq15));
+        CD::st(f + opp(q) * qs + x, (C)fs);
+    });
+    C *m = static_cast<C *>(mom);
+    m[x] = (C)r;
+    m[n + x] = (C)ux;
+    m[2 * (long long)n + x] = (C)uy;
+    m[3 * (long long)n + x] = (C)uz;
+    m[4 * (long long)n + x] = (C)0;
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, const double *fin,
+                                                    int n) {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    T *f = static_cast<T *>(fp);
+    static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        CD::st(f + opp(q) * qs + x, (C)(fin[(long long)q * n + x] - weight(q)));
+    });
+}
+
+// post-collision populations f*_q(x) from the in-place buffer: after a local
+// step (parity 0 next) they sit in slot opp(q) of x; after a neighbour step
+// (parity 1 next) where the neighbour step wrote them.
+template <int ST>
+__global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs, double *fout,
+                                                    int nx, int ny, int nz, int parity,
+                                                    int bc_lo, int bc_hi) {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    const long long n = (long long)nx * ny * nz;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const T *f = static_cast<const T *>(fp);
+    const int i = (int)(x % nx);
+    const int j = (int)((x / nx) % ny);
+    const int k = (int)(x / ((long long)nx * ny));
+    static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+        long long src;
+        int slot;
+        if (parity == 0) {
+            slot = opp(q);
+            src = x;
+        } else {
+            const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
+            const int jt = j + cy;
+            if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
+                if ((jt < 0 ? bc_lo : bc_hi) == BC_BOUNCEBACK) {
+                    slot = opp(q);
+                    src = x;
+                } else {
+                    slot = mir(q);
+                    src = ((long long)kt * ny + j) * nx + it;
+                }
+            } else {
+                slot = q;
+                src = ((long long)kt * ny + (jt + ny) % ny) * nx + it;
+            }
+        }
+        fout[q * n + x] = (double)CD::ld(f + slot * qs + src) + weight(q);
+    });
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void moments_out_kernel(const void *mom, double *rho,
+                                                          double *u, double *nut, int n) {
+    using C = typename Codec<ST>::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const C *m = static_cast<const C *>(mom);
+    const long long N = n;
+    if (rho) rho[x] = (double)m[x];
+    if (u) {
+        u[x] = (double)m[N + x];
+        u[N + x] = (double)m[2 * N + x];
+        u[2 * N + x] = (double)m[3 * N + x];
+    }
+    if (nut) nut[x] = (double)m[4 * N + x];
+}
+
+// pass 1: block b reduces cells [b*chunk, (b+1)*chunk) in FP64:
+// mass, rho u (3), max |u|, non-finite count
+template <int ST>
+__global__ __launch_bounds__(256) void diag_partial_kernel(const void *mom, int n, int chunk,
+                                                           double *partial) {
+    using C = typename Codec<ST>::C;
+    const C *m = static_cast<const C *>(mom);
+    const long long N = n;
+    const int beg = blockIdx.x * chunk;
+    const int end = min(n, beg + chunk);
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int x = beg + threadIdx.x; x < end; x += blockDim.x) {
+        const double r = m[x], ux = m[N + x], uy = m[2 * N + x], uz = m[3 * N + x];
+        const double nt = m[4 * N + x];
+        if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(nt))) {
+            s[5] += 1.0;
+            continue;
+        }
+        s[0] += r;
+        s[1] += r * ux;
+        s[2] += r * uy;
+        s[3] += r * uz;
+        s[4] = fmax(s[4], sqrt(ux * ux + uy * uy + uz * uz));
+    }
+    __shared__ double sh[6][256];
+    for (int c = 0; c < 6; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int c = 0; c < 6; ++c) {
+                if (c == 4)
+                    sh[c][threadIdx.x] = fmax(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
+                else
+                    sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// pass 2 (one block): fixed-order sums of the partials and of the impulse
+// accumulators.  out: mass, mom[3], impulse[3], max|u|, nonfinite
+__global__ __launch_bounds__(256) void diag_final_kernel(const double *partial, int nblocks,
+                                                         const double *imp, int nimp,
+                                                         double *out) {
+    __shared__ double sh[9][256];
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        s[0] += partial[b * 6 + 0];
+        s[1] += partial[b * 6 + 1];
+        s[2] += partial[b * 6 + 2];
+        s[3] += partial[b * 6 + 3];
+        s[7] = fmax(s[7], partial[b * 6 + 4]);
+        s[8] += partial[b * 6 + 5];
+    }
+    for (int b = threadIdx.x; b < nimp; b += blockDim.x) {
+        s[4] += imp[3 * b + 0];
+        s[5] += imp[3 * b + 1];
+        s[6] += imp[3 * b + 2];
+    }
+    for (int c = 0; c < 9; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int c = 0; c < 9; ++c) {
+                if (c == 7)
+                    sh[c][threadIdx.x] = fmax(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
+                else
+                    sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// one block per row j: fixed-order sum over the tiles of the row
+__global__ __launch_bounds__(256) void stats_read_kernel(const double *stats, int tpp,
+                                                         double *prof) {
+    const int j = blockIdx.x;
+    __shared__ double sh[10][256];
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double *row = stats + (long long)j * tpp * 10;
+    for (int t = threadIdx.x; t < tpp; t += blockDim.x)
+        for (int c = 0; c < 10; ++c) s[c] += row[t * 10 + c];
+    for (int c = 0; c < 10; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 10; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 10) prof[j * 10 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n) {
+    const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
+}
+
+}  // namespace
+
+#define LBMX_DISPATCH(storage, CALL)                 \
+    switch (storage) {                               \
+    case ST_F64: { constexpr int S = ST_F64; CALL; } break;     \
+    case ST_F32: { constexpr int S = ST_F32; CALL; } break;     \
+    case ST_F16S: { constexpr int S = ST_F16S; CALL; } break;   \
+    case ST_BF16S: { constexpr int S = ST_BF16S; CALL; } break; \
+    default: return hipErrorInvalidValue;            \
+    }
+
+static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
+    if (bx * bz != 256 || a.ntiles < 1) return hipErrorInvalidValue;
+    dim3 block(bx, bz), grid(a.ntiles);
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(lbm_step_kernel<S>, grid, block, 0, s, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, void *f, long long qs, void *mom, const double *rho,
+                       const double *u, int n, hipStream_t s) {
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+                                              s, f, qs, mom, rho, u, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
+                        hipStream_t s) {
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+                                              s, f, qs, fin, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
+                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(get_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+                                              s, f, qs, fout, nx, ny, nz, parity, bc_lo, bc_hi));
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
+                              double *nut, int n, hipStream_t s) {
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(moments_out_kernel<S>, dim3(blocks_for(n)),
+                                              dim3(256), 0, s, mom, rho, u, nut, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, int nimp,
+                       double *partial, int nblocks, double *out, hipStream_t s) {
+    const int chunk = (n + nblocks - 1) / nblocks;
+    const int nb = (n + chunk - 1) / chunk;
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(diag_partial_kernel<S>, dim3(nb), dim3(256), 0, s,
+                                              mom, n, chunk, partial));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partial, nb, imp, nimp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_read(const double *stats, int ny, int tpp, double *prof,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(stats_read_kernel, dim3(ny), dim3(256), 0, s, stats, tpp, prof);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, double v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbmx

@@ -1,0 +1,28 @@
+// mlp_device.h -- learned eddy-viscosity closure on the device (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+namespace lbmx {
+
+// bytes of the device-side closure parameters (packed from the blob)
+constexpr size_t kMlpDeviceBytes = 32768;
+
+// Validate a closure blob and pack it into the device layout (dev:
+// kMlpDeviceBytes).  false with a reason for a bad magic, version, shape or
+// size.
+bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why);
+
+// fused step with the learned closure
+hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipStream_t s);
+
+// cells of the last step that fell back to Smagorinsky
+lbm_status mlp_fallback_count(const void *dev, int64_t *count, hipStream_t s);
+
+}  // namespace lbmx

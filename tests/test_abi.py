@@ -1,0 +1,84 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/lbm.h declares, and its host-only routines (direction table, LAD
+profile, parameter validation) agree with the oracle.  No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2206_15454_amd import lbm as m
+
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2206_15454_amd import build
+
+        build.build()
+    m.lib()
+    return m
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lbm):
+    names = _declared()
+    assert len(names) >= 15
+    L = lbm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbm.EXPORTS) == names
+
+
+def test_lattice_table_matches_oracle(lbm):
+    c, w = lbm.lattice()
+    co, wo = ref.lattice()
+    np.testing.assert_array_equal(c, co)
+    np.testing.assert_array_equal(w, wo)
+
+
+@pytest.mark.parametrize("args", [(12.0, 8.4, 1.0, 2.0, 128), (10.0, 6.5, 0.38, 0.0, 16),
+                                  (24.0, 16.8, 1.0, 2.0, 256), (7.0, 4.9, 0.38, 0.0, 140)])
+def test_lad_profile_matches_oracle(lbm, args):
+    h, ym, afm, lai, ny = args
+    a = lbm.lad_lalic(h, ym, ny, afm=afm, lai=lai)
+    b = ref.lad_lalic(h, ym, ny, afm=afm, lai=lai)
+    np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)
+
+
+def test_lad_rejects_bad_parameters(lbm):
+    for bad in ((10.0, 12.0), (0.0, 0.0), (-3.0, 1.0)):
+        with pytest.raises(lbm.LBMError):
+            lbm.lad_lalic(bad[0], bad[1], 8)
+
+
+def test_parameter_validation_without_device(lbm):
+    L = lbm.lib()
+
+    def P(**kw):
+        d = dict(nx=8, ny=4, nz=4, storage=1, tau0=0.6, c_smag=0.01, bc_ylo=1, bc_yhi=2)
+        d.update(kw)
+        return lbm.Params(d["nx"], d["ny"], d["nz"], d["storage"], d["tau0"], d["c_smag"],
+                          (C.c_double * 3)(0, 0, 0), d["bc_ylo"], d["bc_yhi"], None)
+
+    assert L.lbm_required_bytes(C.byref(P())) > 19 * 8 * 4 * 4 * 4
+    for bad in (dict(tau0=0.5), dict(nx=0), dict(storage=7), dict(bc_ylo=0),
+                dict(c_smag=-1.0), dict(bc_yhi=5), dict(nx=2048, ny=1024, nz=1024)):
+        assert L.lbm_required_bytes(C.byref(P(**bad))) == 0, bad
+        h = C.c_void_p()
+        assert L.lbm_create(C.byref(P(**bad)), None, 0, C.byref(h)) == 1
+        assert not h.value
+    # storage sizes scale the population buffer
+    b = [L.lbm_required_bytes(C.byref(P(nx=512, ny=64, nz=64, storage=s))) for s in range(4)]
+    assert b[0] > b[1] > b[2] == b[3]
+    assert L.lbm_last_error(None) == b"lbm: NULL context"

@@ -1,0 +1,207 @@
+"""Parity of the HIP fused step (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+  * FP64 storage: normwise max|gpu - oracle| / max|oracle| <= 1e-12 per field
+    after 200 steps of the 64x32x32 canopy case (the arithmetic differs only in
+    operation order: shifted moments, fused multiply-adds).
+  * One step from a stored state S (any storage T): the GPU result equals the
+    oracle step of decode(S) rounded into T, up to one unit in the last place
+    of T plus the FP32 arithmetic error (a few FP32 ulps of the population
+    magnitude) where T is not FP64.
+  * Multi-step, low precision: per-field normwise bounds stated in each test.
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2206_15454_amd import inputs
+from tests.gpu_common import make_pair, normwise, require_gpu, round_storage, ulp
+
+pytestmark = pytest.mark.gpu
+
+_, W = ref.lattice()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _compare_moments(o, g):
+    ro, uo, no, do = o.moments()
+    rg, ug, ng, dg = g.moments()
+    return {"rho": normwise(rg, ro), "u": normwise(ug, uo), "nut": normwise(ng, no)}, do, dg
+
+
+def test_f64_canopy_200_steps_matches_oracle():
+    w = inputs.C1
+    o, g = make_pair(w)
+    o.step(w.steps)
+    g.step(w.steps)
+    err, do, dg = _compare_moments(o, g)
+    print("f64 64x32x32 200 steps normwise:", err)
+    assert err["rho"] <= 1e-12 and err["u"] <= 1e-12 and err["nut"] <= 1e-12
+    assert dg["t"] == 200 and dg["nonfinite"] == 0
+    assert dg["mass"] == pytest.approx(do["mass"], rel=1e-13)
+    for k in ("mom_x", "mom_y", "mom_z"):
+        assert dg[k] == pytest.approx(do[k], rel=1e-10, abs=1e-14)
+    for k in ("imp_x", "imp_y", "imp_z"):
+        assert dg[k] == pytest.approx(do[k], rel=1e-12, abs=1e-18)
+    assert dg["max_u"] == pytest.approx(do["max_u"], rel=1e-12)
+
+
+@pytest.mark.parametrize("shape,bcs", [
+    ((37, 5, 3), (1, 2)),     # ragged x, tiny y
+    ((70, 4, 5), (1, 1)),     # channel: bounce-back both walls
+    ((65, 3, 7), (2, 2)),     # free slip both
+    ((64, 6, 4), (0, 0)),     # fully periodic
+    ((300, 3, 2), (2, 1)),    # several x tiles with a ragged tail
+    ((8, 1, 9), (1, 2)),      # a single row between the walls
+])
+def test_f64_boundaries_and_ragged_grids(shape, bcs):
+    nx, ny, nz = shape
+    w = inputs.scaled(inputs.C1, nx, ny, nz, bc_lo=bcs[0], bc_hi=bcs[1],
+                      canopy_rows=max(1, ny // 2), g=(2e-5, 1e-6, -3e-6))
+    o, g = make_pair(w, seed=17, vector_drag=(nx % 2 == 1))
+    o.step(25)
+    g.step(25)
+    err, do, dg = _compare_moments(o, g)
+    print(shape, bcs, err)
+    assert max(err.values()) <= 1e-12
+    assert dg["mass"] == pytest.approx(do["mass"], rel=1e-13)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_one_step_from_stored_state(storage):
+    """Both AA parities: step 1 (neighbour access) and step 2 (local)."""
+    w = inputs.scaled(inputs.C1, 67, 9, 5, canopy_rows=4)
+    o, g = make_pair(w, storage=storage, init=False)
+    S = inputs.random_populations(w.shape, seed=5, base=W, scale=0.02)
+    shifted = round_storage(S - W[:, None, None, None], storage)
+    S = shifted + W[:, None, None, None]
+    o.set_f(S)
+    g.set_f(S)
+    np.testing.assert_array_equal(g.get_f() - W[:, None, None, None], shifted)
+    for step in (1, 2):
+        o.step(1)
+        g.step(1)
+        fo = o.get_f()
+        fg = g.get_f()
+        so = fo - W[:, None, None, None]
+        sg = fg - W[:, None, None, None]
+        err = np.abs(sg - so)
+        if storage == "f64":
+            bound = 4e-16 * np.max(np.abs(fo))
+        else:
+            # 1 ulp of T at the value + FP32 arithmetic slack (8 FP32 ulps of
+            # the largest shifted population of the cell's direction)
+            scale = np.max(np.abs(so), axis=(1, 2, 3), keepdims=True)
+            bound = ulp(so, storage) + 8 * 2.0 ** -24 * scale
+        worst = float(np.max(err / bound))
+        print(storage, "step", step, "max err/bound", worst)
+        assert worst <= 1.0
+        # the state after the step is representable in T
+        np.testing.assert_array_equal(round_storage(sg, storage), sg)
+        # then restart both from the GPU-rounded state for the next parity
+        S = fg
+        o.set_f(S)
+
+
+@pytest.mark.parametrize("storage,bounds", [
+    ("f32", {"rho": 1e-7, "u": 1e-5, "nut": 1e-3}),
+    ("f16s", {"rho": 1e-4, "u": 2e-3, "nut": 5e-2}),
+    ("bf16s", {"rho": 1e-3, "u": 2e-2, "nut": 2e-1}),
+])
+def test_low_precision_canopy_200_steps(storage, bounds):
+    w = inputs.C1
+    o, g = make_pair(w, storage=storage)
+    o.step(w.steps)
+    g.step(w.steps)
+    err, do, dg = _compare_moments(o, g)
+    print(storage, "64x32x32 200 steps normwise:", err)
+    for k, b in bounds.items():
+        assert err[k] <= b, (k, err[k], b)
+
+
+def test_stats_match_oracle():
+    w = inputs.scaled(inputs.C1, 40, 10, 6)
+    o, g = make_pair(w, seed=3)
+    for s in (o, g):
+        s.stats_reset()
+        s.stats_enable(3)
+    o.step(20)
+    g.step(11)
+    g.step(9)
+    po, no = o.stats_read()
+    pg, ng = g.stats_read()
+    assert no == ng == 6
+    np.testing.assert_allclose(pg, po, rtol=1e-12, atol=1e-22)
+    g.stats_reset()
+    assert g.stats_read()[1] == 0
+
+
+def test_checkpoint_roundtrip_is_bit_identical():
+    w = inputs.scaled(inputs.C1, 48, 12, 8)
+    _, a = make_pair(w, storage="f32", seed=9)
+    _, b = make_pair(w, storage="f32", seed=9)
+    a.step(21)
+    b.step(10)
+    f = b.get_f()
+    b.set_f(f)
+    b.step(11)
+    np.testing.assert_array_equal(a.get_f(), b.get_f())
+    np.testing.assert_array_equal(a.moments()[1], b.moments()[1])
+
+
+def test_tile_width_does_not_change_fp64_results(monkeypatch):
+    w = inputs.scaled(inputs.C1, 300, 6, 5)
+    res = []
+    for bx in ("64", "128", "256"):
+        monkeypatch.setenv("LBMX_BX", bx)
+        for remap in ("0", "1"):
+            monkeypatch.setenv("LBMX_XCD_REMAP", remap)
+            _, g = make_pair(w, seed=4)
+            g.step(12)
+            res.append(g.get_f())
+    for r in res[1:]:
+        np.testing.assert_array_equal(r, res[0])
+
+
+def test_errors_and_state_machine():
+    from paper_2206_15454_amd import lbm
+
+    with pytest.raises(lbm.LBMError):
+        lbm.LBM(8, 4, 4, "f32", tau0=0.5)
+    with pytest.raises(lbm.LBMError):
+        lbm.LBM(8, 4, 4, "f32", bc_lo="periodic", bc_hi="freeslip")
+    g = lbm.LBM(8, 4, 4, "f32")
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(1)
+    assert e.value.status == 4  # ESTATE before init
+    with pytest.raises(lbm.LBMError):
+        g.set_canopy(0.2, np.zeros(3))
+    with pytest.raises(lbm.LBMError):
+        g.set_canopy(0.2, -np.ones(4))
+    # an unstable state is reported and blocks further steps
+    g.init(np.ones(g.shape), np.full((3,) + g.shape, 0.3))
+    with pytest.raises(lbm.LBMError) as e:
+        g.moments()
+    assert e.value.status == 5
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(1)
+    assert e.value.status == 4
+
+
+def test_momentum_balance_periodic_f32():
+    """Fully periodic without canopy: sum(rho u) gains sum(F) per step; the
+    FP64 impulse accumulator equals t * M * g."""
+    w = inputs.scaled(inputs.C1, 64, 8, 8, bc_lo=0, bc_hi=0, canopy_rows=0,
+                      g=(1e-5, 0.0, 0.0))
+    _, g = make_pair(w, storage="f32", seed=2)
+    g.step(1)
+    d0 = g.diag()
+    g.step(50)
+    d1 = g.diag()
+    M = d0["mass"]
+    assert d1["mom_x"] - d0["mom_x"] == pytest.approx(50 * M * 1e-5, rel=1e-4)
+    assert d1["imp_x"] == pytest.approx(51 * M * 1e-5, rel=1e-6)
