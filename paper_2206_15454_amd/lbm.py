@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbmx.so")
+LIB_PATH = os.environ.get("LBMX_LIB") or os.path.join(_HERE, "liblbmx.so")
 
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 BC = {"periodic": 0, "bounceback": 1, "freeslip": 2}

@@ -91,7 +91,9 @@ def test_one_step_from_stored_state(storage):
         sg = fg - W[:, None, None, None]
         err = np.abs(sg - so)
         if storage == "f64":
-            bound = 4e-16 * np.max(np.abs(fo))
+            # the oracle rounds relative to |f| (unshifted), the GPU relative to
+            # |f - w|: 16 FP64 ulps of the largest population
+            bound = 16 * 2.0 ** -53 * np.max(np.abs(fo))
         else:
             # 1 ulp of T at the value + FP32 arithmetic slack (8 FP32 ulps of
             # the largest shifted population of the cell's direction)
@@ -108,7 +110,7 @@ def test_one_step_from_stored_state(storage):
 
 
 @pytest.mark.parametrize("storage,bounds", [
-    ("f32", {"rho": 1e-7, "u": 1e-5, "nut": 1e-3}),
+    ("f32", {"rho": 1e-6, "u": 2e-5, "nut": 1e-4}),
     ("f16s", {"rho": 1e-4, "u": 2e-3, "nut": 5e-2}),
     ("bf16s", {"rho": 1e-3, "u": 2e-2, "nut": 2e-1}),
 ])
@@ -135,7 +137,10 @@ def test_stats_match_oracle():
     po, no = o.stats_read()
     pg, ng = g.stats_read()
     assert no == ng == 6
-    np.testing.assert_allclose(pg, po, rtol=1e-12, atol=1e-22)
+    # means of signed quantities cancel: the tolerance is relative to the
+    # largest value of each column
+    atol = 1e-11 * np.max(np.abs(po), axis=0, keepdims=True)
+    assert np.all(np.abs(pg - po) <= 1e-12 * np.abs(po) + atol)
     g.stats_reset()
     assert g.stats_read()[1] == 0
 
