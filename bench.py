@@ -119,6 +119,10 @@ def main():
     ap.add_argument("--variants", default="f64,f16s,bf16s",
                     help="other storage types timed on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp", action="store_true",
+                    help="also time the learned closure (bf16s storage) on the same workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -135,6 +139,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel(), "copy_bytes_written": y.numel(),
+                          "launches": 3}), flush=True)
+        return
     w = inputs.C2
     rho, u = inputs.init_fields(w)
     rho_d = torch.from_numpy(rho).cuda()
@@ -161,6 +174,21 @@ def main():
         b = 2 * 19 * BYTES_PER_ELT[st] * w.n
         variants[st] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
                         "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    if args.mlp:
+        from paper_2206_15454_amd import closure
+
+        sim = make_sim(w, "bf16s", lbm, inputs)
+        sim.init(rho_d, u_d)
+        # a network with every feature in range: the closure runs in every cell
+        sim.set_closure(closure.timing_blob(w.lad_lalic[0]))
+        k = max(50, args.steps // 4)
+        t_ms, s_ms, d = time_steps(sim, k, 20, torch)
+        sim.close()
+        variants["bf16s+mlp"] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+                                 "hbm_frac": round(2 * 19 * 2 * w.n / (s_ms * 1e-3 / k) / 1e9
+                                                   / HBM_PEAK_GBS, 4),
+                                 "mlp_fallback": d["mlp_fallback"]}
 
     out = {
         "metric": METRIC,

@@ -46,13 +46,14 @@ enum : int {
 };
 
 // Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
-// non-temporal (streaming) cache policy; every population is touched once
-// per step, so there is no reuse for the caches to keep.
+// non-temporal (streaming) cache policy.  Measured on MI355X, the default
+// cached policy is faster for both: the neighbour step's x-shifted accesses
+// share cache lines between adjacent tiles, which meet in one XCD's L2.
 #ifndef LBMX_NT_LOAD
 #define LBMX_NT_LOAD 0
 #endif
 #ifndef LBMX_NT_STORE
-#define LBMX_NT_STORE 1
+#define LBMX_NT_STORE 0
 #endif
 template <class T> __device__ __forceinline__ T pop_ld(const T *p) {
 #if LBMX_NT_LOAD

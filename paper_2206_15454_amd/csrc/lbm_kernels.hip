@@ -21,6 +21,7 @@
 // opposite direction; free slip moves it tangentially within the wall row
 // with the y component reversed.
 #include "lbm_device.h"
+#include "mlp_closure.h"
 
 namespace lbmx {
 
@@ -53,15 +54,15 @@ __device__ __forceinline__ void block_accumulate(const C (&v)[K], double *acc, d
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
+// One tile (BX x 1 x BZ cells of row j) of one fused time step.
+template <int ST, bool LEARNED>
+__device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
+                                          short *zst, double *sh) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
     T *__restrict__ f = static_cast<T *>(a.f);
 
-    int tile = blockIdx.x;
-    if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
     const int bx = tile % a.nbx;
     const int rest = tile / a.nbx;
     const int bz = rest % a.nbz;
@@ -166,7 +167,34 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     // tau = (tau0 + sqrt(tau0^2 + X))/2, X = 18 sqrt2 C Q^(1/2)/rho, written
     // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
     const C X = (C)a.ksmag * Qh * irho;
-    const C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
+    C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
+    if constexpr (LEARNED) {
+        // learned closure where the features are inside the trained range,
+        // Smagorinsky (above) elsewhere
+        const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+        const int lane = tid & 63;
+        MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
+        float x[9];
+        mlp_features((float)nxx, (float)nyy, (float)nzz, (float)nxy, (float)nxz, (float)nyz,
+                     (float)rho, ((float)j + 0.5f) * P->inv_h, (float)lad, x);
+        bool in_range = true;
+        short z[16];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            in_range = in_range && (x[c] >= P->lo[c]) && (x[c] <= P->hi[c]);
+            z[c] = bf16_bits((x[c] - P->mean[c]) * P->istd[c]);
+        }
+        z[9] = z[10] = bf16_bits(1.0f);
+#pragma unroll
+        for (int c = 11; c < 16; ++c) z[c] = 0;
+        __syncthreads();  // the previous tile's reads of the staging area are done
+        mlp_stage_inputs(zst, lane, z);
+        __syncthreads();
+        const float o = mlp_forward_wave(frag, zst, lane) + P->b3;
+        if (in_range) nut = (C)(P->scale * mlp_softplus(o));
+        const unsigned long long fb = __ballot(!in_range && active);
+        if (lane == 0 && fb) atomicAdd(&P->fallback[a.parity], (unsigned long long)__popcll(fb));
+    }
     const C tau = tau0 + C(3) * nut;
     const C itau = C(1) / tau;
 
@@ -224,7 +252,6 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     }
 
     // ---- body-force impulse and plane statistics (FP64 accumulators) ------
-    __shared__ double sh[4 * 10];
     if (a.flags & FLAG_IMPULSE) {
         const C z = 0;
         const C fv[3] = {active ? Fx : z, active ? Fy : z, active ? Fz : z};
@@ -237,6 +264,33 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
                           m * uz * uz, m * ux * uy, m * ux * uz, m * uy * uz, m * nut};
         const long long slot = ((long long)j * (a.nbx * a.nbz) + bz * a.nbx + bx) * 10;
         block_accumulate<10>(sv, a.stats + slot, sh);
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
+    __shared__ double sh[4 * 10];
+    int tile = blockIdx.x;
+    if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
+    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh);
+}
+
+// Learned closure: persistent blocks keep the network's weight fragments in
+// registers and walk the tiles (linear index it = block + k * grid; with the
+// grid a multiple of 8, every tile of a block stays on the block's XCD).
+template <int ST>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 3, ST == ST_F64 ? 2 : 3)))
+void lbm_step_mlp_kernel(const StepArgs a) {
+    __shared__ double sh[4 * 10];
+    __shared__ __attribute__((aligned(16))) short zst[4][64 * 16];
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
+    if (blockIdx.x == 0 && tid == 0) P->fallback[a.parity ^ 1] = 0;  // for the next step
+    const MlpFrag frag = mlp_load_frag(P, tid & 63);
+    for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
+        const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
+        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh);
     }
 }
 
@@ -462,6 +516,23 @@ hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream
     if (bx * bz != 256 || a.ntiles < 1) return hipErrorInvalidValue;
     dim3 block(bx, bz), grid(a.ntiles);
     LBMX_DISPATCH(storage, hipLaunchKernelGGL(lbm_step_kernel<S>, grid, block, 0, s, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
+    if (bx * bz != 256 || a.ntiles < 1 || a.mlp == nullptr) return hipErrorInvalidValue;
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    LBMX_DISPATCH(storage, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S>), 256, 0));
+    if (e != hipSuccess) return e;
+    int grid = (per_cu > 0 ? per_cu : 1) * ncu;
+    grid = grid >= 8 ? grid / 8 * 8 : grid;
+    if (grid > a.ntiles) grid = a.ntiles;
+    LBMX_DISPATCH(storage, hipLaunchKernelGGL(lbm_step_mlp_kernel<S>, dim3(grid), dim3(bx, bz), 0,
+                                              s, a));
     return hipGetLastError();
 }
 

@@ -1,0 +1,164 @@
+// mlp_closure.h -- device side of the learned eddy-viscosity closure
+// (internal).  A 9-64-64-1 network with BF16 operands on the matrix cores
+// and FP32 accumulation, evaluated for the 64 cells of a wavefront at once.
+//
+// Formulation: activations are kept transposed (units x cells), so that one
+// 16x16 MFMA output tile (lane l holds rows 4*(l/16)+r, r = 0..3, of column
+// l%16) is directly the B operand of the next 16x16x32 MFMA (lane l holds
+// rows 8*(l/16)+t, t = 0..7, of column l%16) once the k index is permuted the
+// same way in the weights: no data moves between lanes from layer to layer.
+//   layer 1: mfma 16x16x16 bf16, A = [W1 | b1_hi b1_lo | 0] (16 units x 16 k),
+//            B = [z0..z8, 1, 1, 0..] of 16 cells
+//   layer 2: mfma 16x16x32 bf16 (two k steps), A = W2/2 with permuted k,
+//            C initialised with b2 (the inputs are 2 gelu)
+//   output : o = b3 + (w3/2) . 2gelu(h2) (FP32 FMAs, then a sum over the four
+//            lane quarters of a column)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmx {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpIn = 9, kMlpH1 = 64, kMlpH2 = 64;
+constexpr int kMlpParams = kMlpH1 * kMlpIn + kMlpH1 + kMlpH2 * kMlpH1 + kMlpH2 + kMlpH2 + 1;
+
+// Packed device parameters (written by mlp_pack on the host).
+struct MlpParams {
+    float mean[12], istd[12], lo[12], hi[12];  // raw-feature standardisation and range
+    float scale, inv_h, b3, pad0;
+    short4v w1f[4][64];      // layer-1 A fragments [unit tile][lane]
+    bf16x8 w2f[4][2][64];    // layer-2 A fragments [unit tile][k step][lane]
+    floatx4 b2f[4][4];       // layer-2 bias in output layout [unit tile][lane quarter]
+    floatx4 w3f[4][4];       // output weights in output layout [unit tile][lane quarter]
+    unsigned long long fallback[2];  // cells that fell back, per step parity
+};
+
+// input unit of layer 2 that k slot (k step ks, lane quarter h, element t)
+// of the B operand holds: the layer-1 output tiles 2ks and 2ks+1 side by side
+__host__ __device__ constexpr int mlp_l2_unit_in(int ks, int h, int t) {
+    return 32 * ks + (t < 4 ? 4 * h + t : 16 + 4 * h + (t - 4));
+}
+
+// per-lane weight fragments held in registers for the life of a wave
+struct MlpFrag {
+    short4v w1[4];
+    bf16x8 w2[4][2];
+    floatx4 b2[4];
+    floatx4 w3[4];
+};
+
+__device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane) {
+    MlpFrag f;
+    const int h = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        f.w1[u] = p->w1f[u][lane];
+        f.w2[u][0] = p->w2f[u][0][lane];
+        f.w2[u][1] = p->w2f[u][1][lane];
+        f.b2[u] = p->b2f[u][h];
+        f.w3[u] = p->w3f[u][h];
+    }
+    return f;
+}
+
+// Twice the GELU (tanh form x/2 (1 + tanh(a)), a = sqrt(2/pi)(x + 0.044715 x^3)),
+// without transcendentals: 2 gelu(x) = x + x tanh(a(x)); the even function
+// x tanh(a(x)) is a polynomial in y = x^2 on y <= 3.4^2 (least-squares,
+// near-minimax degree 5) and |x| beyond.  Max |error| of gelu: 9.3e-4, below
+// the bf16 rounding of the activations it feeds.  The factor 1/2 is folded
+// exactly into the next layer's weights (W2/2, w3/2) when the blob is packed.
+__device__ __forceinline__ float mlp_gelu2(float x) {
+    const float y = x * x;
+    float e = 2.013099584e-05f;
+    e = __builtin_fmaf(e, y, -7.981360541e-04f);
+    e = __builtin_fmaf(e, y, 1.303727739e-02f);
+    e = __builtin_fmaf(e, y, -1.175806001e-01f);
+    e = __builtin_fmaf(e, y, 7.844402790e-01f);
+    e = __builtin_fmaf(e, y, 1.860028133e-03f);
+    e = (y <= 11.56f) ? e : __builtin_fabsf(x);
+    return x + e;
+}
+
+__device__ __forceinline__ float mlp_softplus(float x) {
+    return x > 20.0f ? x : __logf(1.0f + __expf(x));
+}
+
+__device__ __forceinline__ short bf16_bits(float x) {
+    __bf16 b = (__bf16)x;  // round to nearest even
+    return __builtin_bit_cast(short, b);
+}
+
+// Raw features of one cell from Pi_neq (6 components), rho, row data.
+// P = Pi_neq / (rho/3); n = e_y.
+__device__ __forceinline__ void mlp_features(float nxx, float nyy, float nzz, float nxy,
+                                             float nxz, float nyz, float rho, float yh,
+                                             float lad, float (&x)[9]) {
+    const float s = 3.0f / rho;
+    const float a = nxx * s, b = nyy * s, c = nzz * s, d = nxy * s, e = nxz * s, f = nyz * s;
+    // P^2 (symmetric)
+    const float q_xx = a * a + d * d + e * e;
+    const float q_yy = d * d + b * b + f * f;
+    const float q_zz = e * e + f * f + c * c;
+    const float q_xy = a * d + d * b + e * f;
+    const float q_xz = a * e + d * f + e * c;
+    const float q_yz = d * e + b * f + f * c;
+    const float tr2 = q_xx + q_yy + q_zz;
+    const float tr3 = q_xx * a + q_yy * b + q_zz * c + 2.0f * (q_xy * d + q_xz * e + q_yz * f);
+    x[0] = a + b + c;
+    x[1] = tr2;
+    x[2] = tr3;
+    x[3] = b;
+    x[4] = q_yy;
+    x[5] = sqrtf(tr2);
+    x[6] = yh;
+    x[7] = lad;
+    x[8] = 1.0f;
+}
+
+// Learned nu_t for the 64 cells of this wave (one cell per lane).  z: this
+// lane's 16 standardised inputs as bf16 bits (z0..z8, 1, 1, 0...), lds: 64 x 16
+// shorts of this wave's scratch.  The caller orders the LDS write/read.
+__device__ __forceinline__ void mlp_stage_inputs(short *lds, int lane, const short (&z)[16]) {
+    typedef short short8v __attribute__((ext_vector_type(8)));
+    short8v lo = {z[0], z[1], z[2], z[3], z[4], z[5], z[6], z[7]};
+    short8v hi = {z[8], z[9], z[10], z[11], z[12], z[13], z[14], z[15]};
+    *reinterpret_cast<short8v *>(lds + lane * 16) = lo;
+    *reinterpret_cast<short8v *>(lds + lane * 16 + 8) = hi;
+}
+
+// o (pre-softplus output, without b3) for this lane's cell
+__device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short *lds, int lane) {
+    const int h = lane >> 4, col = lane & 15;
+    float mine = 0.0f;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const short4v zb = *reinterpret_cast<const short4v *>(lds + (16 * ct + col) * 16 + 4 * h);
+        bf16x8 x2[2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[u], zb, zero, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x2[u >> 1][(u & 1) * 4 + r] = (__bf16)mlp_gelu2(d[r]);
+        }
+        float part = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[u][0], x2[0], f.b2[u], 0, 0, 0);
+            e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[u][1], x2[1], e, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part += f.w3[u][r] * mlp_gelu2(e[r]);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (h == ct) mine = part;
+    }
+    return mine;
+}
+
+}  // namespace lbmx

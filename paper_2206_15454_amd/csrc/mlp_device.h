@@ -22,7 +22,7 @@ bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why)
 // fused step with the learned closure
 hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipStream_t s);
 
-// cells of the last step that fell back to Smagorinsky
-lbm_status mlp_fallback_count(const void *dev, int64_t *count, hipStream_t s);
+// cells of the step with the given parity that fell back to Smagorinsky
+lbm_status mlp_fallback_count(const void *dev, int parity, int64_t *count, hipStream_t s);
 
 }  // namespace lbmx

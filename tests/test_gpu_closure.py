@@ -1,0 +1,115 @@
+"""Learned closure in the fused step (MFMA inference) against the oracle.
+
+Tolerance: the GPU evaluates the network with BF16 operands (inputs and
+hidden activations rounded to 8 significant bits) and FP32 accumulation; the
+oracle evaluates the same BF16-rounded weights in FP64 on unrounded inputs.
+Each rounding is <= 2^-9 relative; through two layers and the softplus this
+bounds the error of nu_t by a few percent of its scale: the tests use 3e-2
+of max |nu_t| (one step).  Where the closure falls back, nu_t is the
+Smagorinsky value and follows the FP64 bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2206_15454_amd import closure, inputs
+from tests.gpu_common import make_pair, normwise, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+MEAN = np.array([0, 0, 0, 0, 0, 1e-3, 1.5, 0.1, 1.0])
+STD = np.array([1e-4, 1e-6, 1e-9, 1e-3, 1e-6, 1e-3, 1.0, 0.15, 1.0])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(size=(64, 9)) / 3.0
+    b1 = rng.normal(size=64) * 0.1
+    W2 = rng.normal(size=(64, 64)) / 8.0
+    b2 = rng.normal(size=64) * 0.1
+    w3 = rng.normal(size=64) / 8.0
+    return closure.join(W1, b1, W2, b2, w3, -0.5)
+
+
+def blob_with_range(lo, hi, seed=1, scale=1e-4, h=10.0):
+    return closure.make_blob(random_params(seed), MEAN, STD, lo, hi, scale, h)
+
+
+WIDE_LO = np.full(9, -1e30)
+WIDE_HI = np.full(9, 1e30)
+
+
+def test_blob_validation():
+    from paper_2206_15454_amd import lbm
+
+    g = lbm.LBM(16, 4, 4, "f32")
+    good = blob_with_range(WIDE_LO, WIDE_HI)
+    g.set_closure(good)
+    for bad in (good[:-1], b"XXXX" + good[4:], good[:4] + b"\x02" + good[5:]):
+        with pytest.raises(lbm.LBMError):
+            g.set_closure(bad)
+    std0 = closure.make_blob(random_params(1), MEAN, np.zeros(9), WIDE_LO, WIDE_HI, 1e-4, 10.0)
+    with pytest.raises(lbm.LBMError):
+        g.set_closure(std0)
+    g.set_closure(None)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s"])
+def test_all_fallback_equals_smagorinsky_bitwise(storage):
+    w = inputs.scaled(inputs.C1, 96, 12, 8)
+    _, a = make_pair(w, storage=storage, seed=2)
+    _, b = make_pair(w, storage=storage, seed=2)
+    lo = WIDE_LO.copy()
+    hi = WIDE_HI.copy()
+    lo[8], hi[8] = 2.0, 3.0  # the width feature is 1: every cell is out of range
+    b.set_closure(blob_with_range(lo, hi))
+    a.step(15)
+    b.step(15)
+    # the populations (which carry the dynamics) are bit-identical
+    np.testing.assert_array_equal(a.get_f(), b.get_f())
+    ra, ua, na, da = a.moments()
+    rb, ub, nb, db = b.moments()
+    np.testing.assert_array_equal(ua, ub)
+    # the FP32 nu_t output may differ in its last bit (instruction selection
+    # differs between the two kernels; tau and everything after it agree)
+    assert np.max(np.abs(na - nb) / np.maximum(np.abs(nb), 1e-30)) <= 2 * 2.0 ** -23
+    assert db["mlp_fallback"] == w.n and da["mlp_fallback"] == 0
+
+
+def test_learned_closure_matches_oracle():
+    w = inputs.scaled(inputs.C1, 48, 16, 8, canopy_rows=5)
+    o, g = make_pair(w, storage="f64", seed=6)
+    lo = WIDE_LO.copy()
+    hi = WIDE_HI.copy()
+    hi[7] = 0.15  # LAD above 0.15: the canopy rows fall back to Smagorinsky
+    blob = blob_with_range(lo, hi, seed=3)
+    m = ref.MLP(blob)
+    o.set_closure(m)
+    g.set_closure(blob)
+    o.step(1)
+    g.step(1)
+    ro, uo, no, do = o.moments()
+    rg, ug, ng, dg = g.moments()
+    canopy = np.zeros(w.shape, dtype=bool)
+    canopy[:, :5, :] = True
+    assert do["mlp_fallback"] == dg["mlp_fallback"] == canopy.sum()
+    # fallback rows: Smagorinsky in FP64
+    assert normwise(ng[canopy], no[canopy]) <= 1e-12
+    # learned rows: BF16 operands
+    e_mlp = normwise(ng[~canopy], no[~canopy])
+    print("learned nu_t normwise error after 1 step:", e_mlp, "max nu_t", no[~canopy].max())
+    assert e_mlp <= 3e-2
+    assert normwise(ug, uo) <= 1e-6
+    # a few more steps stay close
+    o.step(9)
+    g.step(9)
+    ro, uo, no, do = o.moments()
+    rg, ug, ng, dg = g.moments()
+    print("after 10 steps: u", normwise(ug, uo), "nu_t", normwise(ng, no))
+    assert normwise(ug, uo) <= 1e-5
+    assert normwise(ng, no) <= 5e-2
