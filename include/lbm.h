@@ -182,6 +182,59 @@ lbm_status lbm_get_f(lbm_ctx *ctx, double *f, int32_t on_device);
  * h <= 0, ym outside [0, h), ny < 1 or NULL out. */
 lbm_status lbm_lad_lalic(double h, double ym, double afm, double lai, int32_t ny, double *out);
 
+/* ------------------------------------------------------------------------
+ * Learned closure: training data and training (design of this library; the
+ * paper names other SGS models as future work, Sec. 6).
+ * ---------------------------------------------------------------------- */
+
+/* Training samples from a run at twice the resolution.  `fine` must have
+ * even nx, ny, nz and hold the moments of its latest step (lbm_step called).
+ * The coarse grid is (nx/2, ny/2, nz/2).  For every coarse cell (FP32):
+ *   - box-filtered velocity ub and the subfilter stress
+ *     tau = box(u u) - ub ub + box(-2 nu_t^f S^f), S^f the fine strain rate by
+ *     central differences of the fine velocity (one-sided next to y walls,
+ *     periodic in x and z), in coarse lattice units (velocity unchanged);
+ *   - the coarse strain Sb of ub by central differences on the coarse grid;
+ *   - the target nu_t* = max(0, -tau_dev : Sb / (2 Sb : Sb)) (0 where Sb = 0);
+ *   - the 9 closure features of the stress a coarse LBM would carry,
+ *     P = -2 (tau0_coarse + 3 nu_t*) Sb: tr P, tr P^2, tr P^3, P_yy, (P^2)_yy,
+ *     sqrt(tr P^2), (j + 1/2)/canopy_h, lad_coarse[j], 1.
+ * X: device [nc][9], y: device [nc], nc = (nx/2)(ny/2)(nz/2) (cell order
+ * [z][y][x]).  lad_coarse: host, ny/2 values.  EINVAL for odd dimensions, NULL
+ * pointers or nc mismatch; ESTATE before lbm_init. */
+lbm_status lbm_closure_samples(lbm_ctx *fine, double tau0_coarse, double canopy_h,
+                               const double *lad_coarse, float *X, float *y, int64_t nc);
+
+typedef struct lbm_trainer lbm_trainer; /* opaque */
+
+typedef struct lbm_train_params {
+    float mean[9], std[9];   /* feature standardisation z = (x - mean)/std, std > 0 */
+    float out_scale;         /* s: the network's softplus output is nu_t / s */
+    float lr, beta1, beta2, eps; /* Adam */
+    int32_t max_batch;       /* largest batch passed to lbm_train_step */
+    void *stream;            /* hipStream_t or NULL */
+} lbm_train_params;
+
+/* A trainer for the 9-64-64-1 closure network: FP32 master parameters
+ * (flat order W1[64][9], b1[64], W2[64][64], b2[64], w3[64], b3; 4865 values,
+ * host array `params`, copied), Adam moments, BF16 MFMA fragments. */
+lbm_status lbm_train_create(const lbm_train_params *prm, const float *params, lbm_trainer **out);
+
+/* Gradient of L = (1/n) sum (softplus(o) - y/s)^2 over one batch (device X
+ * [n][9] raw features, device y [n] target nu_t) with BF16 operands and FP32
+ * accumulation on the matrix cores; with update != 0 one Adam step follows.
+ * loss_out (host, may be NULL; synchronises) receives L.  EINVAL for n < 1 or
+ * n > max_batch. */
+lbm_status lbm_train_step(lbm_trainer *tr, const float *X, const float *y, int64_t n,
+                          int32_t update, float *loss_out);
+
+/* Copy the FP32 master parameters and/or the last gradient (host, 4865
+ * values each; either may be NULL).  Synchronises. */
+lbm_status lbm_train_get(lbm_trainer *tr, float *params, float *grad);
+
+lbm_status lbm_train_destroy(lbm_trainer *tr);
+const char *lbm_train_last_error(const lbm_trainer *tr);
+
 #ifdef __cplusplus
 }
 #endif

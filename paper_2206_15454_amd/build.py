@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmx.so")
-SOURCES = ["lbm_kernels.hip", "mlp_kernels.hip", "lbm_api.hip"]
+SOURCES = ["lbm_kernels.hip", "mlp_kernels.hip", "lbm_api.hip", "mlp_train.hip",
+           "closure_data.hip"]
 ARCH = os.environ.get("LBMX_ARCH", "gfx950")
 
 

@@ -512,6 +512,34 @@ lbm_status lbm_get_f(lbm_ctx *c, double *fout, int32_t on_device) {
     return LBM_OK;
 }
 
+lbm_status lbm_closure_samples(lbm_ctx *c, double tau0_coarse, double canopy_h,
+                               const double *lad_coarse, float *X, float *y, int64_t nc) {
+    if (!c) return LBM_EINVAL;
+    if (!c->inited) return fail(c, LBM_ESTATE, "lbm_closure_samples: call lbm_init first");
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    if ((nx | ny | nz) & 1) return fail(c, LBM_EINVAL, "lbm_closure_samples: dimensions must be even");
+    if (!X || !y || !lad_coarse) return fail(c, LBM_EINVAL, "lbm_closure_samples: NULL pointer");
+    const long long ncc = (long long)(nx / 2) * (ny / 2) * (nz / 2);
+    if (nc != ncc) return fail(c, LBM_EINVAL, "lbm_closure_samples: nc must be (nx/2)(ny/2)(nz/2)");
+    if (!(canopy_h > 0.0) || !(tau0_coarse > 0.5))
+        return fail(c, LBM_EINVAL, "lbm_closure_samples: canopy_h > 0 and tau0_coarse > 0.5");
+    float *work = nullptr;
+    double *lad_d = nullptr;
+    HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&work), (size_t)9 * ncc * 4, c->stream),
+           "lbm_closure_samples: work");
+    HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&lad_d), (size_t)(ny / 2) * 8, c->stream),
+           "lbm_closure_samples: lad");
+    HIPCHK(c, hipMemcpyAsync(lad_d, lad_coarse, (size_t)(ny / 2) * 8, hipMemcpyHostToDevice, c->stream),
+           "lbm_closure_samples: copy lad");
+    HIPCHK(c, launch_closure_samples(c->p.storage, c->mom, nx, ny, nz, work, tau0_coarse,
+                                     1.0 / canopy_h, lad_d, X, y, c->stream),
+           "lbm_closure_samples: kernels");
+    HIPCHK(c, hipFreeAsync(work, c->stream), "lbm_closure_samples: free");
+    HIPCHK(c, hipFreeAsync(lad_d, c->stream), "lbm_closure_samples: free");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_closure_samples: sync");
+    return LBM_OK;
+}
+
 lbm_status lbm_lad_lalic(double h, double ym, double afm, double lai, int32_t ny, double *out) {
     if (!out || ny < 1 || !(h > 0.0) || !(ym >= 0.0) || !(ym < h) || !std::isfinite(h))
         return LBM_EINVAL;

@@ -157,5 +157,9 @@ hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, i
 hipError_t launch_stats_read(const double *stats, int ny, int tpp, double *prof,
                              hipStream_t s);
 hipError_t launch_fill(double *p, double v, size_t n, hipStream_t s);
+// closure_data.hip: work holds 9 planes of (nx/2)(ny/2)(nz/2) floats
+hipError_t launch_closure_samples(int storage, const void *mom, int nx, int ny, int nz,
+                                  float *work, double tau0_coarse, double inv_h,
+                                  const double *lad_coarse, float *X, float *Y, hipStream_t s);
 
 }  // namespace lbmx

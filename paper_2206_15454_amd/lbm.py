@@ -43,9 +43,17 @@ class Diag(C.Structure):
                 "nonfinite": self.nonfinite, "mlp_fallback": self.mlp_fallback}
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("mean", C.c_float * 9), ("std", C.c_float * 9), ("out_scale", C.c_float),
+                ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("max_batch", C.c_int32), ("stream", C.c_void_p)]
+
+
 EXPORTS = ("lbm_lattice", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_last_error",
            "lbm_set_stream", "lbm_set_canopy", "lbm_set_closure", "lbm_init", "lbm_step",
-           "lbm_moments", "lbm_stats", "lbm_set_f", "lbm_get_f", "lbm_lad_lalic")
+           "lbm_moments", "lbm_stats", "lbm_set_f", "lbm_get_f", "lbm_lad_lalic",
+           "lbm_closure_samples", "lbm_train_create", "lbm_train_step", "lbm_train_get",
+           "lbm_train_destroy", "lbm_train_last_error")
 
 _lib = None
 
@@ -88,6 +96,18 @@ def lib():
         L.lbm_get_f.argtypes = [vp, vp, i32]
         L.lbm_lad_lalic.restype = i32
         L.lbm_lad_lalic.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+        L.lbm_closure_samples.restype = i32
+        L.lbm_closure_samples.argtypes = [vp, C.c_double, C.c_double, dp, vp, vp, i64]
+        L.lbm_train_create.restype = i32
+        L.lbm_train_create.argtypes = [C.POINTER(TrainParams), C.POINTER(C.c_float), C.POINTER(vp)]
+        L.lbm_train_step.restype = i32
+        L.lbm_train_step.argtypes = [vp, vp, vp, i64, i32, C.POINTER(C.c_float)]
+        L.lbm_train_get.restype = i32
+        L.lbm_train_get.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.lbm_train_destroy.restype = i32
+        L.lbm_train_destroy.argtypes = [vp]
+        L.lbm_train_last_error.restype = C.c_char_p
+        L.lbm_train_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -254,3 +274,77 @@ class LBM:
             p = C.c_void_p(out.ctypes.data)
         self._check(lib().lbm_get_f(self.h, p, int(device)), "lbm_get_f")
         return out
+
+    def closure_samples(self, tau0_coarse, canopy_h, lad_coarse):
+        """(X [nc, 9], y [nc]) float32 torch tensors on the device: training
+        samples of the learned closure from this (fine) simulation."""
+        torch = self.torch
+        nz, ny, nx = self.shape
+        nc = (nx // 2) * (ny // 2) * (nz // 2)
+        X = torch.empty((nc, 9), dtype=torch.float32, device="cuda")
+        y = torch.empty(nc, dtype=torch.float32, device="cuda")
+        lad = np.ascontiguousarray(lad_coarse, dtype=np.float64)
+        self._check(lib().lbm_closure_samples(self.h, float(tau0_coarse), float(canopy_h),
+                                              lad.ctypes.data_as(C.POINTER(C.c_double)),
+                                              C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                                              nc), "lbm_closure_samples")
+        return X, y
+
+
+class Trainer:
+    """GPU trainer of the closure network (MFMA forward/backward + Adam)."""
+
+    NPARAM = 4865
+
+    def __init__(self, params, mean, std, out_scale, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 max_batch=8192, stream=None):
+        import torch
+
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        prm = TrainParams((C.c_float * 9)(*map(float, mean)), (C.c_float * 9)(*map(float, std)),
+                          float(out_scale), float(lr), float(betas[0]), float(betas[1]),
+                          float(eps), int(max_batch), C.c_void_p(self.stream.cuda_stream))
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.NPARAM:
+            raise ValueError("expected 4865 parameters")
+        h = C.c_void_p()
+        st = lib().lbm_train_create(C.byref(prm), p.ctypes.data_as(C.POINTER(C.c_float)),
+                                    C.byref(h))
+        if st != 0:
+            raise LBMError(st, "lbm_train_create")
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def _check(self, st, what):
+        if st != 0:
+            raise LBMError(st, f"{what}: {lib().lbm_train_last_error(self.h).decode()}")
+
+    def step(self, X, y, update=True, loss=True):
+        """One batch (torch float32 cuda tensors X [n, 9], y [n]); returns the
+        loss (before the update) if requested."""
+        X = X.contiguous()
+        y = y.contiguous()
+        out = C.c_float(0.0)
+        self._check(lib().lbm_train_step(self.h, C.c_void_p(X.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), int(y.numel()), int(update),
+                                         C.byref(out) if loss else None), "lbm_train_step")
+        return out.value if loss else None
+
+    def get(self):
+        p = np.zeros(self.NPARAM, dtype=np.float32)
+        g = np.zeros(self.NPARAM, dtype=np.float32)
+        self._check(lib().lbm_train_get(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                        g.ctypes.data_as(C.POINTER(C.c_float))), "lbm_train_get")
+        return p, g
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_train_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
