@@ -55,9 +55,17 @@ __device__ __forceinline__ void block_accumulate(const C (&v)[K], double *acc, d
 }
 
 // One tile (BX x 1 x BZ cells of row j) of one fused time step.
+// wave-local ordering of LDS accesses (each wave stages into its own region)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int ST, bool LEARNED>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
-                                          short *zst, double *sh) {
+                                          short *zst, double *sh, double (&imp)[3],
+                                          typename Codec<ST>::C *pst) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
@@ -187,10 +195,19 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         z[9] = z[10] = bf16_bits(1.0f);
 #pragma unroll
         for (int c = 11; c < 16; ++c) z[c] = 0;
-        __syncthreads();  // the previous tile's reads of the staging area are done
+        // park the populations in LDS while the network runs (frees registers)
+        static_for<NQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            pst[q * 256 + tid] = v[q];
+        });
+        wave_lds_sync();  // the previous tile's reads of this wave's staging area are done
         mlp_stage_inputs(zst, lane, z);
-        __syncthreads();
+        wave_lds_sync();
         const float o = mlp_forward_wave(frag, zst, lane) + P->b3;
+        static_for<NQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            v[q] = pst[q * 256 + tid];
+        });
         if (in_range) nut = (C)(P->scale * mlp_softplus(o));
         const unsigned long long fb = __ballot(!in_range && active);
         if (lane == 0 && fb) atomicAdd(&P->fallback[a.parity], (unsigned long long)__popcll(fb));
@@ -255,10 +272,18 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     if (a.flags & FLAG_IMPULSE) {
         const C z = 0;
         const C fv[3] = {active ? Fx : z, active ? Fy : z, active ? Fz : z};
-        block_accumulate<3>(fv, a.imp + 3 * (long long)tile, sh);
+        if constexpr (LEARNED) {
+            // persistent blocks: per-thread FP64 sums over the block's tiles,
+            // reduced once at the end of the kernel
+            imp[0] += (double)fv[0];
+            imp[1] += (double)fv[1];
+            imp[2] += (double)fv[2];
+        } else {
+            block_accumulate<3>(fv, a.imp + 3 * (long long)tile, sh);
+        }
     }
     if (a.flags & FLAG_STATS) {
-        if (a.flags & FLAG_IMPULSE) __syncthreads();  // sh reused
+        if (!LEARNED && (a.flags & FLAG_IMPULSE)) __syncthreads();  // sh reused
         const C m = active ? C(1) : C(0);
         const C sv[10] = {m * ux,      m * uy,      m * uz,      m * ux * ux, m * uy * uy,
                           m * uz * uz, m * ux * uy, m * ux * uz, m * uy * uz, m * nut};
@@ -272,7 +297,8 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     __shared__ double sh[4 * 10];
     int tile = blockIdx.x;
     if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
-    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh);
+    double unused[3] = {0.0, 0.0, 0.0};
+    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr);
 }
 
 // Learned closure: persistent blocks keep the network's weight fragments in
@@ -284,13 +310,22 @@ __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 3, ST == ST_F64 ? 2 : 3)))
 void lbm_step_mlp_kernel(const StepArgs a) {
     __shared__ double sh[4 * 10];
     __shared__ __attribute__((aligned(16))) short zst[4][64 * 16];
+    __shared__ typename Codec<ST>::C pst[NQ * 256];  // populations parked during the network
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
     if (blockIdx.x == 0 && tid == 0) P->fallback[a.parity ^ 1] = 0;  // for the next step
-    const MlpFrag frag = mlp_load_frag(P, tid & 63);
+    __shared__ bf16x8 w2s[4 * 2 * 64];
+    mlp_stage_w2(P, w2s, tid, 256);
+    __syncthreads();
+    const MlpFrag frag = mlp_load_frag(P, tid & 63, w2s);
+    double imp[3] = {0.0, 0.0, 0.0};
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh);
+        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh, imp, pst);
+    }
+    if (a.flags & FLAG_IMPULSE) {
+        __syncthreads();  // sh may still be read by the last tile's statistics
+        block_accumulate<3>(imp, a.imp + 3 * (long long)blockIdx.x, sh);  // grid <= ntiles
     }
 }
 

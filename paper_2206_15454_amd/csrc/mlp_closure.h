@@ -44,26 +44,35 @@ __host__ __device__ constexpr int mlp_l2_unit_in(int ks, int h, int t) {
     return 32 * ks + (t < 4 ? 4 * h + t : 16 + 4 * h + (t - 4));
 }
 
-// per-lane weight fragments held in registers for the life of a wave
+// per-lane weight fragments held in registers for the life of a wave; the
+// layer-2 fragments (8 KB per block) live in LDS and are read per MFMA
 struct MlpFrag {
     short4v w1[4];
-    bf16x8 w2[4][2];
     floatx4 b2[4];
     floatx4 w3[4];
+    const bf16x8 *w2;  // LDS copy of MlpParams::w2f, [unit tile][k step][lane]
 };
 
-__device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane) {
+__device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane,
+                                                 const bf16x8 *w2_lds) {
     MlpFrag f;
     const int h = lane >> 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         f.w1[u] = p->w1f[u][lane];
-        f.w2[u][0] = p->w2f[u][0][lane];
-        f.w2[u][1] = p->w2f[u][1][lane];
         f.b2[u] = p->b2f[u][h];
         f.w3[u] = p->w3f[u][h];
     }
+    f.w2 = w2_lds;
     return f;
+}
+
+// copy the layer-2 fragments into LDS (all threads of the block; the caller
+// synchronises before use)
+__device__ __forceinline__ void mlp_stage_w2(const MlpParams *p, bf16x8 *w2_lds, int tid,
+                                             int nthreads) {
+    const bf16x8 *src = &p->w2f[0][0][0];
+    for (int i = tid; i < 4 * 2 * 64; i += nthreads) w2_lds[i] = src[i];
 }
 
 // Twice the GELU (tanh form x/2 (1 + tanh(a)), a = sqrt(2/pi)(x + 0.044715 x^3)),
@@ -149,8 +158,10 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short 
         float part = 0.0f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[u][0], x2[0], f.b2[u], 0, 0, 0);
-            e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[u][1], x2[1], e, 0, 0, 0);
+            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[(2 * u) * 64 + lane], x2[0],
+                                                                f.b2[u], 0, 0, 0);
+            e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[(2 * u + 1) * 64 + lane], x2[1], e,
+                                                        0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) part += f.w3[u][r] * mlp_gelu2(e[r]);
         }
