@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("MLUPS and % of HBM roofline; low-precision+learned vs plain FP32 at "
           "≤1% profile error")
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_ELT = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+BYTES_PER_ELT = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2, "bf16sr": 2}
 KERNEL_SOURCES = ("paper_2206_15454_amd/csrc/lbm_kernels.hip",
                   "paper_2206_15454_amd/csrc/lbm_device.h")
 

@@ -49,8 +49,12 @@ typedef enum {
  * (w_i the lattice weight) so that the small deviations from rest keep their
  * digits; F32 storage is shifted as well, F64 stores the same shifted value in
  * double.  Arithmetic is FP64 for LBM_F64 and FP32 for the others.
- * Rounding into storage is round-to-nearest-even. */
-typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
+ * Rounding into storage is round-to-nearest-even, except LBM_BF16SR: BF16
+ * with stochastic rounding (rounds up with probability equal to the dropped
+ * fraction; the random bits are a hash of the step, the cell and the
+ * direction, so runs are reproducible).  Initial and imported states are
+ * rounded to nearest. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_BF16SR = 4 } lbm_storage;
 
 /* Wall-normal (y) boundaries.  BOUNCEBACK is the halfway no-slip wall;
  * FREESLIP is specular reflection (a symmetry plane); PERIODIC must be set

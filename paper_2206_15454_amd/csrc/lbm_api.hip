@@ -69,7 +69,8 @@ size_t storage_bytes(int st) {
     case LBM_F64: return 8;
     case LBM_F32: return 4;
     case LBM_F16S:
-    case LBM_BF16S: return 2;
+    case LBM_BF16S:
+    case LBM_BF16SR: return 2;
     default: return 0;
     }
 }
@@ -366,6 +367,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->closure == LBM_CLOSURE_MLP) base_flags |= FLAG_MLP;
     for (int64_t s = 0; s < nsteps; ++s) {
         a.parity = c->parity;
+        a.seed = (uint32_t)(c->t * 0x9E3779B97F4A7C15ULL >> 32) ^ 0x5bd1e995u;
         a.flags = base_flags;
         if (s == nsteps - 1) a.flags |= FLAG_MOMENTS;
         const bool sample = c->stats_every > 0 && (c->t + 1) % c->stats_every == 0;

@@ -33,7 +33,7 @@ constexpr double weight(int q) {
 }
 
 enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2 };
-enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3, ST_BF16SR = 4 };
 
 // step flags
 enum : int {
@@ -71,25 +71,26 @@ template <class T> __device__ __forceinline__ void pop_st(T *p, T v) {
 }
 
 // Storage codecs: T is the element type in HBM, C the arithmetic type.
-// Stored values are shifted populations f_q - w_q.
+// Stored values are shifted populations f_q - w_q.  st() takes 32 random bits
+// (used only by the stochastically rounded type).
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
     using T = double;
     using C = double;
     static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v) { pop_st(p, v); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, v); }
 };
 template <> struct Codec<ST_F32> {
     using T = float;
     using C = float;
     static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v) { pop_st(p, v); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, v); }
 };
 template <> struct Codec<ST_F16S> {
     using T = _Float16;
     using C = float;
     static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v) {
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) {
         pop_st(p, (_Float16)v);  // round to nearest even
     }
 };
@@ -97,10 +98,36 @@ template <> struct Codec<ST_BF16S> {
     using T = __bf16;
     using C = float;
     static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v) {
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) {
         pop_st(p, (__bf16)v);  // v_cvt_pk_bf16_f32, nearest even
     }
 };
+// BF16 with stochastic rounding: adding 16 uniform random bits below the kept
+// mantissa and truncating rounds up with probability equal to the dropped
+// fraction, so the rounding error has zero mean (finite values).
+template <> struct Codec<ST_BF16SR> {
+    using T = __bf16;
+    using C = float;
+    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t r) {
+        const uint32_t b = __float_as_uint(v) + (r & 0xFFFFu);
+        pop_st(p, __builtin_bit_cast(__bf16, (unsigned short)(b >> 16)));
+    }
+};
+
+// 32-bit integer hash (xorshift-multiply finaliser) for the rounding bits
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// storage handled by the auxiliary (init/import/export) kernels: the
+// stochastically rounded type is read and written there like BF16S
+constexpr int aux_storage(int st) { return st == ST_BF16SR ? ST_BF16S : st; }
 
 // Arguments of one fused step launch (passed by value as kernel arguments).
 struct StepArgs {
@@ -112,6 +139,7 @@ struct StepArgs {
     int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
     int bc_lo, bc_hi;
     int flags;
+    uint32_t seed;    // stochastic rounding: hash of (seed, step, cell, direction)
     double tau0;      // molecular relaxation time
     double ksmag;     // 18 sqrt(2) C_smag
     double g[3];      // driving acceleration

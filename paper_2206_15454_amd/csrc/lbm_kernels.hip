@@ -65,7 +65,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int ST, bool LEARNED>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
                                           short *zst, double *sh, double (&imp)[3],
-                                          typename Codec<ST>::C *pst) {
+                                          typename Codec<ST>::C *pst, unsigned &fallbacks) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
@@ -209,8 +209,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             v[q] = pst[q * 256 + tid];
         });
         if (in_range) nut = (C)(P->scale * mlp_softplus(o));
-        const unsigned long long fb = __ballot(!in_range && active);
-        if (lane == 0 && fb) atomicAdd(&P->fallback[a.parity], (unsigned long long)__popcll(fb));
+        fallbacks += (!in_range && active) ? 1u : 0u;
     }
     const C tau = tau0 + C(3) * nut;
     const C itau = C(1) / tau;
@@ -233,11 +232,16 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     });
 
     // ---- a7: store in place --------------------------------------------------
+    // random bits for stochastic rounding (unused by the other storage types)
+    const uint32_t rbase = (ST == ST_BF16SR) ? mix32(a.seed ^ mix32((uint32_t)self)) : 0u;
+    auto rnd = [&](int q) -> uint32_t {
+        return (ST == ST_BF16SR) ? mix32(rbase + 0x9E3779B9u * (uint32_t)(q + 1)) : 0u;
+    };
     if (active) {
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                CD::st(f + opp(q) * qs + self, v[q]);
+                CD::st(f + opp(q) * qs + self, v[q], rnd(q));
             });
         } else {
             static_for<NQ>([&](auto qc) {
@@ -247,11 +251,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                 if (cy != 0 && (jt < 0 || jt >= ny) &&
                     (jt < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
                     if ((jt < 0 ? a.bc_lo : a.bc_hi) == BC_BOUNCEBACK)
-                        CD::st(f + opp(q) * qs + self, v[q]);
+                        CD::st(f + opp(q) * qs + self, v[q], rnd(q));
                     else
-                        CD::st(f + mir(q) * qs + cell(cx, 0, cz), v[q]);
+                        CD::st(f + mir(q) * qs + cell(cx, 0, cz), v[q], rnd(q));
                 } else {
-                    CD::st(f + q * qs + cell(cx, cy, cz), v[q]);
+                    CD::st(f + q * qs + cell(cx, cy, cz), v[q], rnd(q));
                 }
             });
         }
@@ -298,7 +302,8 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     int tile = blockIdx.x;
     if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
     double unused[3] = {0.0, 0.0, 0.0};
-    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr);
+    unsigned nofb = 0;
+    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr, nofb);
 }
 
 // Learned closure: persistent blocks keep the network's weight fragments in
@@ -319,10 +324,16 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     __syncthreads();
     const MlpFrag frag = mlp_load_frag(P, tid & 63, w2s);
     double imp[3] = {0.0, 0.0, 0.0};
+    unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh, imp, pst);
+        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
+    // cells that fell back: one atomic per wave
+    unsigned fsum = fallbacks;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
+    if ((tid & 63) == 0 && fsum) atomicAdd(&P->fallback[a.parity], (unsigned long long)fsum);
     if (a.flags & FLAG_IMPULSE) {
         __syncthreads();  // sh may still be read by the last tile's statistics
         block_accumulate<3>(imp, a.imp + 3 * (long long)blockIdx.x, sh);  // grid <= ntiles
@@ -542,7 +553,18 @@ __global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n
     case ST_F32: { constexpr int S = ST_F32; CALL; } break;     \
     case ST_F16S: { constexpr int S = ST_F16S; CALL; } break;   \
     case ST_BF16S: { constexpr int S = ST_BF16S; CALL; } break; \
+    case ST_BF16SR: { constexpr int S = ST_BF16SR; CALL; } break; \
     default: return hipErrorInvalidValue;            \
+    }
+
+// auxiliary kernels: the stochastically rounded type maps to BF16S
+#define LBMX_DISPATCH_AUX(storage, CALL)                           \
+    switch (aux_storage(storage)) {                                \
+    case ST_F64: { constexpr int S = ST_F64; CALL; } break;       \
+    case ST_F32: { constexpr int S = ST_F32; CALL; } break;       \
+    case ST_F16S: { constexpr int S = ST_F16S; CALL; } break;     \
+    case ST_BF16S: { constexpr int S = ST_BF16S; CALL; } break;   \
+    default: return hipErrorInvalidValue;                          \
     }
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
@@ -573,14 +595,14 @@ hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipSt
 
 hipError_t launch_init(int storage, void *f, long long qs, void *mom, const double *rho,
                        const double *u, int n, hipStream_t s) {
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
                                               s, f, qs, mom, rho, u, n));
     return hipGetLastError();
 }
 
 hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
                         hipStream_t s) {
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
                                               s, f, qs, fin, n));
     return hipGetLastError();
 }
@@ -588,14 +610,14 @@ hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, i
 hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
                         int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(get_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
+    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(get_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
                                               s, f, qs, fout, nx, ny, nz, parity, bc_lo, bc_hi));
     return hipGetLastError();
 }
 
 hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
                               double *nut, int n, hipStream_t s) {
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(moments_out_kernel<S>, dim3(blocks_for(n)),
+    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(moments_out_kernel<S>, dim3(blocks_for(n)),
                                               dim3(256), 0, s, mom, rho, u, nut, n));
     return hipGetLastError();
 }
@@ -604,7 +626,7 @@ hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, i
                        double *partial, int nblocks, double *out, hipStream_t s) {
     const int chunk = (n + nblocks - 1) / nblocks;
     const int nb = (n + chunk - 1) / chunk;
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(diag_partial_kernel<S>, dim3(nb), dim3(256), 0, s,
+    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(diag_partial_kernel<S>, dim3(nb), dim3(256), 0, s,
                                               mom, n, chunk, partial));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -21,7 +21,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP = 0, 1, 2
-STORAGES = ("f64", "f32", "f16s", "bf16s")
+STORAGES = ("f64", "f32", "f16s", "bf16s", "bf16sr")
 
 
 @dataclass(frozen=True)

@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBMX_LIB") or os.path.join(_HERE, "liblbmx.so")
 
-STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "bf16sr": 4}
 BC = {"periodic": 0, "bounceback": 1, "freeslip": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSTABLE"}
 

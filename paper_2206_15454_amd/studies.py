@@ -1,0 +1,336 @@
+"""Drivers of the studies the metric names (GPU only; results as JSON).
+
+  python -m paper_2206_15454_amd.studies closure   --out DIR
+      learned closure: a run at twice the resolution (1024x256x512, FP32,
+      h = 24) -> training samples at three snapshots -> GPU training (MFMA
+      forward/backward + Adam) -> closure blob -> the production canopy case
+      (512x128x256) with BF16S storage + learned closure against FP32 storage
+      + Smagorinsky (and a perturbed FP32 run for the chaotic noise floor),
+      profiles averaged in time and over x-z; throughput of both forms.
+  python -m paper_2206_15454_amd.studies precision --out DIR
+      storage precision on 1024x256x512 (physics of the 64x32x32 canopy
+      case): FP32 / FP16S / BF16S fields after 1000 steps against the GPU FP64
+      run (itself pinned to the CPU oracle by the parity tests); mean and RMS
+      profiles after a long run; throughput per storage type.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import closure, inputs, lbm
+
+MEAN_COLS = {"u": 0, "v": 1, "w": 2}
+
+
+def _log(*a):
+    print(time.strftime("%H:%M:%S"), *a, flush=True)
+
+
+def _lad(w):
+    if w.lad_lalic is not None:
+        h, ym, lai = w.lad_lalic
+        return lbm.lad_lalic(h, ym, w.ny, lai=lai)
+    return inputs.lad_constant(w)
+
+
+def make(w, storage, rho, u, blob=None):
+    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    sim.set_canopy(w.cd, _lad(w))
+    sim.init(rho, u)
+    if blob is not None:
+        sim.set_closure(blob)
+    return sim
+
+
+def timed_steps(sim, n, torch, chunk=1000, label=""):
+    """n steps in chunks (progress lines); returns GPU ms."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        e0.record()
+        sim.step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+        done += k
+        if label:
+            _log(f"{label}: {done}/{n} steps")
+    return total
+
+
+def profiles(prof):
+    """mean and RMS profiles from the [ny][10] means"""
+    u, v, w = prof[:, 0], prof[:, 1], prof[:, 2]
+    var = np.maximum(prof[:, 3:6] - prof[:, 0:3] ** 2, 0.0)
+    return {"u": u, "v": v, "w": w, "u_rms": np.sqrt(var[:, 0]), "v_rms": np.sqrt(var[:, 1]),
+            "w_rms": np.sqrt(var[:, 2]), "uv": prof[:, 6] - u * v, "nu_t": prof[:, 9]}
+
+
+def coarsen_profile(prof):
+    """[2m][10] means on a fine grid -> [m][10] means on the 2x coarser rows"""
+    return 0.5 * (prof[0::2] + prof[1::2])
+
+
+def profile_errors(a, b):
+    """max_y |a - b| / max_y |b| for the mean and RMS profiles"""
+    pa, pb = profiles(a), profiles(b)
+    out = {}
+    for k in ("u", "u_rms", "v_rms", "w_rms", "uv"):
+        den = np.max(np.abs(pb[k]))
+        out[k] = float(np.max(np.abs(pa[k] - pb[k])) / den) if den > 0 else 0.0
+    return out
+
+
+def field_errors(a, b):
+    """per-field max and RMS error of a against b (normalised by max |b|)"""
+    den = float(np.max(np.abs(b)))
+    d = np.abs(a - b)
+    return {"max": float(d.max() / den), "rms": float(np.sqrt(np.mean(d * d)) / den)}
+
+
+# ---------------------------------------------------------------------------
+# learned closure
+# ---------------------------------------------------------------------------
+
+def closure_study(out, fine_steps=40000, snapshots=(20000, 30000, 40000), coarse_steps=20000,
+                  avg_from=10000, n_train=8_000_000, epochs=3, batch=8192, lr=1e-3):
+    import torch
+
+    dev = torch.device("cuda")
+    res = {"fine": {}, "train": {}, "aposteriori": {}, "mlups": {}}
+    wf, wc = inputs.C4, inputs.C2
+    lad_c = _lad(wc)
+    h_c = wc.lad_lalic[0]
+
+    # 1. the run at twice the resolution, with its own statistics
+    rho, u = inputs.init_fields_torch(wf, dev)
+    fine = make(wf, "f32", rho, u)
+    del rho, u
+    Xs, ys = [], []
+    done = 0
+    ms = 0.0
+    for snap in snapshots:
+        if done < fine_steps // 2 <= snap:
+            ms += timed_steps(fine, fine_steps // 2 - done, torch, 2000, "fine")
+            done = fine_steps // 2
+            fine.stats_reset()
+            fine.stats_enable(20)
+        ms += timed_steps(fine, snap - done, torch, 2000, "fine")
+        done = snap
+        X, y = fine.closure_samples(wc.tau0, h_c, lad_c)
+        Xs.append(X)
+        ys.append(y)
+        _log(f"snapshot at fine step {snap}: {y.numel()} samples, "
+             f"mean target {float(y.mean()):.3e}, nonzero {float((y > 0).float().mean()):.3f}")
+    prof_f, nsf = fine.stats_read()
+    d = fine.diag()
+    res["fine"] = {"cells": wf.n, "steps": done, "ms": ms, "MLUPS": wf.n * done / ms / 1e3,
+                   "stat_samples": nsf, "max_u": d["max_u"]}
+    fine.close()
+    prof_ref = coarsen_profile(prof_f)
+
+    # 2. training set (90/10 split by z slabs of every snapshot), statistics
+    nz = wc.nz
+    per = Xs[0].shape[0]
+    cut = per * 9 // 10
+    Xtr = torch.cat([x[:cut] for x in Xs]).cpu().numpy()
+    ytr = torch.cat([y[:cut] for y in ys]).cpu().numpy()
+    Xva = torch.cat([x[cut:] for x in Xs])
+    yva = torch.cat([y[cut:] for y in ys])
+    del Xs, ys
+    mean = Xtr.mean(axis=0, dtype=np.float64)
+    std = Xtr.std(axis=0, dtype=np.float64)
+    std[std <= 0] = 1.0
+    lo = Xtr.min(axis=0).astype(np.float64)
+    hi = Xtr.max(axis=0).astype(np.float64)
+    s = float(ytr.mean()) if ytr.mean() > 0 else 1e-5
+    rng = np.random.default_rng(7)
+    idx = rng.permutation(Xtr.shape[0])[:n_train]
+    Xd = torch.from_numpy(np.ascontiguousarray(Xtr[idx])).to(dev)
+    yd = torch.from_numpy(np.ascontiguousarray(ytr[idx])).to(dev)
+    var = float(np.var(ytr / s))
+    del Xtr, ytr
+    p0 = closure.join(rng.normal(size=(64, 9)) / 3.0, np.zeros(64),
+                      rng.normal(size=(64, 64)) / 8.0, np.zeros(64),
+                      rng.normal(size=64) / 8.0, math.log(math.e - 1.0))
+    tr = lbm.Trainer(p0, mean, std, s, lr=lr, max_batch=batch)
+    nb = Xd.shape[0] // batch
+    t0 = time.time()
+    hist = []
+    for ep in range(epochs):
+        for b in range(nb):
+            want = (b % 500 == 0)
+            l = tr.step(Xd[b * batch:(b + 1) * batch], yd[b * batch:(b + 1) * batch],
+                        update=True, loss=want)
+            if want:
+                hist.append(l)
+                _log(f"epoch {ep} batch {b}/{nb} loss {l:.4e}")
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+
+    def val_loss():
+        tot, cnt = 0.0, 0
+        for b in range(0, yva.numel() - batch + 1, batch * 8):
+            tot += tr.step(Xva[b:b + batch], yva[b:b + batch], update=False) * batch
+            cnt += batch
+        return tot / max(cnt, 1)
+
+    vl = val_loss()
+    p, _ = tr.get()
+    tr.close()
+    blob = closure.make_blob(p, mean, std, lo, hi, s, h_c)
+    res["train"] = {"samples_train": int(n_train), "epochs": epochs, "batch": batch, "lr": lr,
+                    "seconds": train_s, "steps": epochs * nb,
+                    "samples_per_s": epochs * nb * batch / train_s, "loss_history": hist,
+                    "val_loss": vl, "val_target_variance": var,
+                    "val_explained_variance": 1.0 - vl / var if var > 0 else None,
+                    "out_scale": s, "mean": mean.tolist(), "std": std.tolist(),
+                    "lo": lo.tolist(), "hi": hi.tolist()}
+    with open(os.path.join(out, "closure_blob.bin"), "wb") as f:
+        f.write(blob)
+    _log("training done", json.dumps({k: res["train"][k] for k in ("val_loss", "val_target_variance")}))
+    del Xd, yd, Xva, yva
+
+    # 3. a-posteriori: the production canopy case with each closure/storage
+    rho, u = inputs.init_fields_torch(wc, dev)
+    runs = {"f32_smag": ("f32", None, 0.0), "f32_smag_perturbed": ("f32", None, 1e-7),
+            "f32_mlp": ("f32", blob, 0.0),
+            "bf16s_smag": ("bf16s", None, 0.0), "bf16s_mlp": ("bf16s", blob, 0.0),
+            "bf16sr_smag": ("bf16sr", None, 0.0), "bf16sr_mlp": ("bf16sr", blob, 0.0),
+            "f16s_smag": ("f16s", None, 0.0), "f16s_mlp": ("f16s", blob, 0.0)}
+    profs = {}
+    for name, (st, b, eps) in runs.items():
+        uu = u if eps == 0.0 else u * (1.0 + eps)
+        sim = make(wc, st, rho, uu, b)
+        try:
+            ms = timed_steps(sim, avg_from, torch, 5000, name)
+            sim.stats_reset()
+            sim.stats_enable(10)
+            ms += timed_steps(sim, coarse_steps - avg_from, torch, 5000, name)
+            prof, ns = sim.stats_read()
+            d = sim.diag()
+        except lbm.LBMError as e:
+            res["aposteriori"][name] = {"error": str(e)}
+            _log(name, "failed:", e)
+            sim.close()
+            continue
+        profs[name] = prof
+        res["aposteriori"][name] = {"MLUPS": wc.n * coarse_steps / ms / 1e3, "stat_samples": ns,
+                                    "mlp_fallback_last_step": d["mlp_fallback"],
+                                    "fallback_fraction": d["mlp_fallback"] / wc.n,
+                                    "max_u": d["max_u"], "profile": profiles(prof)["u"].tolist()}
+        sim.close()
+    A = res["aposteriori"]
+    for x in runs:
+        if x != "f32_smag" and x in profs and "f32_smag" in profs:
+            A[f"e_{x}_vs_f32_smag"] = profile_errors(profs[x], profs["f32_smag"])
+    A["noise_floor_f32_perturbed"] = A.pop("e_f32_smag_perturbed_vs_f32_smag", None)
+    for x in runs:
+        if x in profs:
+            A[f"e_{x}_vs_filtered_fine"] = profile_errors(profs[x], prof_ref)
+            A[x]["nu_t_mean"] = float(np.mean(profiles(profs[x])["nu_t"]))
+    A["filtered_fine_profile"] = profiles(prof_ref)["u"].tolist()
+    A["u_tau"] = math.sqrt(wc.g[0] * wc.ny)
+
+    # 4. throughput of both forms at 1024x256x512
+    w5 = inputs.C5
+    rho, u = inputs.init_fields_torch(w5, dev)
+    for name, (st, b) in {"f32_smag": ("f32", None), "bf16s_mlp": ("bf16s", blob),
+                          "bf16s_smag": ("bf16s", None), "f16s_mlp": ("f16s", blob),
+                          "bf16sr_smag": ("bf16sr", None)}.items():
+        sim = make(w5, st, rho, u, b)
+        sim.step(20)
+        ms = timed_steps(sim, 200, torch, 200)
+        res["mlups"][name + "_1024x256x512"] = w5.n * 200 / ms / 1e3
+        sim.close()
+    with open(os.path.join(out, "closure_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    _log("closure study:", json.dumps({"aposteriori": {k: v["u"] for k, v in A.items()
+                                                      if k.startswith(("e_", "noise")) and v},
+                                      "mlups": res["mlups"]}))
+    return res
+
+
+# ---------------------------------------------------------------------------
+# precision
+# ---------------------------------------------------------------------------
+
+def precision_study(out, steps=1000, long_steps=20000, avg_from=10000,
+                    storages=("f32", "f16s", "bf16s", "bf16sr")):
+    import torch
+
+    dev = torch.device("cuda")
+    w = inputs.C3
+    rho, u = inputs.init_fields_torch(w, dev)
+    res = {"workload": w.name, "steps": steps, "fields": {}, "mlups": {}, "profiles": {}}
+    ref = make(w, "f64", rho, u)
+    ms = timed_steps(ref, steps, torch, 500, "f64")
+    res["mlups"]["f64"] = w.n * steps / ms / 1e3
+    r0, u0, n0, _ = ref.moments(device=True)
+    ref.close()
+    for st in storages:
+        sim = make(w, st, rho, u)
+        ms = timed_steps(sim, steps, torch, 500, st)
+        res["mlups"][st] = w.n * steps / ms / 1e3
+        r1, u1, n1, _ = sim.moments(device=True)
+        sim.close()
+        fe = {}
+        for name, a, b in (("rho", r1, r0), ("u", u1, u0), ("nu_t", n1, n0)):
+            d = (a - b).abs()
+            den = float(b.abs().max())
+            fe[name] = {"max": float(d.max()) / den, "rms": float(d.pow(2).mean().sqrt()) / den}
+        res["fields"][st] = fe
+        _log(st, json.dumps(fe))
+        del r1, u1, n1
+    del r0, u0, n0
+    if long_steps:
+        profs = {}
+        for st, eps in (("f32", 0.0), ("bf16s", 0.0), ("bf16sr", 0.0), ("f16s", 0.0),
+                        ("f32_perturbed", 1e-7)):
+            sim = make(w, st.split("_")[0], rho, u if eps == 0.0 else u * (1.0 + eps))
+            timed_steps(sim, avg_from, torch, 5000, st)
+            sim.stats_reset()
+            sim.stats_enable(10)
+            timed_steps(sim, long_steps - avg_from, torch, 5000, st)
+            profs[st] = sim.stats_read()[0]
+            sim.close()
+        for st in ("bf16s", "bf16sr", "f16s", "f32_perturbed"):
+            res["profiles"][st + "_vs_f32"] = profile_errors(profs[st], profs["f32"])
+        _log("profiles:", json.dumps(res["profiles"]))
+    with open(os.path.join(out, "precision_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["closure", "precision"])
+    ap.add_argument("--out", default="gpurun_out")
+    ap.add_argument("--fine-steps", type=int, default=40000)
+    ap.add_argument("--coarse-steps", type=int, default=20000)
+    ap.add_argument("--long-steps", type=int, default=20000)
+    args = ap.parse_args()
+    import torch
+
+    if not torch.cuda.is_available():
+        sys.exit("the studies need a GPU")
+    torch.cuda.set_device(0)
+    os.makedirs(args.out, exist_ok=True)
+    if args.study == "closure":
+        f = args.fine_steps
+        closure_study(args.out, fine_steps=f, snapshots=(f // 2, 3 * f // 4, f),
+                      coarse_steps=args.coarse_steps, avg_from=args.coarse_steps // 2)
+    else:
+        precision_study(args.out, long_steps=args.long_steps, avg_from=args.long_steps // 2)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,7 +57,7 @@ def round_storage(x, storage):
         return np.asarray(x, dtype=np.float32).astype(np.float64)
     if storage == "f16s":
         return np.asarray(x, dtype=np.float16).astype(np.float64)
-    if storage == "bf16s":
+    if storage in ("bf16s", "bf16sr"):
         f = np.asarray(x, dtype=np.float32)  # exact for the values used (already f32)
         b = f.view(np.uint32).astype(np.uint64)
         b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
@@ -68,7 +68,8 @@ def round_storage(x, storage):
 def ulp(x, storage):
     """unit in the last place of |x| in the storage type (x is the shifted value)."""
     a = np.abs(np.asarray(x, dtype=np.float64))
-    mant = {"f64": 52, "f32": 23, "f16s": 10, "bf16s": 7}[storage]
-    tiny = {"f64": 2.0 ** -1022, "f32": 2.0 ** -126, "f16s": 2.0 ** -14, "bf16s": 2.0 ** -126}[storage]
+    mant = {"f64": 52, "f32": 23, "f16s": 10, "bf16s": 7, "bf16sr": 7}[storage]
+    tiny = {"f64": 2.0 ** -1022, "f32": 2.0 ** -126, "f16s": 2.0 ** -14, "bf16s": 2.0 ** -126,
+            "bf16sr": 2.0 ** -126}[storage]
     e = np.floor(np.log2(np.maximum(a, tiny)))
     return 2.0 ** (e - mant)

@@ -71,7 +71,7 @@ def test_f64_boundaries_and_ragged_grids(shape, bcs):
     assert dg["mass"] == pytest.approx(do["mass"], rel=1e-13)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "bf16sr"])
 def test_one_step_from_stored_state(storage):
     """Both AA parities: step 1 (neighbour access) and step 2 (local)."""
     w = inputs.scaled(inputs.C1, 67, 9, 5, canopy_rows=4)
@@ -113,6 +113,7 @@ def test_one_step_from_stored_state(storage):
     ("f32", {"rho": 1e-6, "u": 2e-5, "nut": 1e-4}),
     ("f16s", {"rho": 1e-4, "u": 2e-3, "nut": 5e-2}),
     ("bf16s", {"rho": 1e-3, "u": 2e-2, "nut": 2e-1}),
+    ("bf16sr", {"rho": 1e-3, "u": 2e-2, "nut": 2e-1}),
 ])
 def test_low_precision_canopy_200_steps(storage, bounds):
     w = inputs.C1
@@ -210,3 +211,29 @@ def test_momentum_balance_periodic_f32():
     M = d0["mass"]
     assert d1["mom_x"] - d0["mom_x"] == pytest.approx(50 * M * 1e-5, rel=1e-4)
     assert d1["imp_x"] == pytest.approx(51 * M * 1e-5, rel=1e-6)
+
+
+def test_stochastic_rounding_is_unbiased():
+    """BF16SR: one step from a stored state rounds each population to one of
+    its two BF16 neighbours with zero-mean error (in units of the BF16 ulp),
+    while round-to-nearest keeps the error within half an ulp."""
+    w = inputs.scaled(inputs.C1, 128, 16, 8, canopy_rows=4)
+    errs = {}
+    for st in ("bf16s", "bf16sr"):
+        o, g = make_pair(w, storage=st, init=False)
+        S = inputs.random_populations(w.shape, seed=21, base=W, scale=0.02)
+        S = round_storage(S - W[:, None, None, None], st) + W[:, None, None, None]
+        o.set_f(S)
+        g.set_f(S)
+        o.step(1)
+        g.step(1)
+        so = o.get_f() - W[:, None, None, None]
+        sg = g.get_f() - W[:, None, None, None]
+        errs[st] = (sg - so) / ulp(so, st)
+    e_rn, e_sr = errs["bf16s"], errs["bf16sr"]
+    print("signed error in ulps: RN mean %.4f max %.3f; SR mean %.4f max %.3f std %.3f" % (
+        e_rn.mean(), np.abs(e_rn).max(), e_sr.mean(), np.abs(e_sr).max(), e_sr.std()))
+    assert np.abs(e_rn).max() <= 0.5 + 1e-3
+    assert np.abs(e_sr).max() <= 1.0 + 1e-3
+    assert abs(e_sr.mean()) <= 0.02
+    assert 0.2 <= e_sr.std() <= 0.5  # stochastic: not always the nearest neighbour
