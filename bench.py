@@ -90,8 +90,11 @@ def cpu_baseline(w, target_s=10.0):
 
     nz = max(1, min(w.nz, 16))
     ws = inputs.scaled(w, w.nx, w.ny, nz)
-    h, ym, lai = w.lad_lalic
-    lad = ref.lad_lalic(h, ym, w.ny, lai=lai)
+    if w.lad_lalic is not None:
+        h, ym, lai = w.lad_lalic
+        lad = ref.lad_lalic(h, ym, w.ny, lai=lai)
+    else:
+        lad = inputs.lad_constant(w)
     sim = ref.RefLBM(ws.nx, ws.ny, ws.nz, ws.tau0, ws.c_smag, ws.g, ws.bc_lo, ws.bc_hi)
     sim.set_canopy(ws.cd, lad)
     rho, u = inputs.init_fields(ws)
@@ -116,14 +119,18 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_ELT))
-    ap.add_argument("--variants", default="f64,f16s,bf16s",
+    ap.add_argument("--variants", default="f64,f16s,bf16s,bf16sr",
                     help="other storage types timed on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp", action="store_true",
-                    help="also time the learned closure (bf16s storage) on the same workload")
+                    help="also time the learned closure on the same workload")
+    ap.add_argument("--mlp-storage", default="bf16sr", choices=list(BYTES_PER_ELT))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
+                    help="c2: production canopy 512x128x256 (default); c3/c5: 1024x256x512 "
+                         "with the 64x32x32 case's physics (profiling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,10 +155,13 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel(), "copy_bytes_written": y.numel(),
                           "launches": 3}), flush=True)
         return
-    w = inputs.C2
-    rho, u = inputs.init_fields(w)
-    rho_d = torch.from_numpy(rho).cuda()
-    u_d = torch.from_numpy(u).cuda()
+    w = {"c2": inputs.C2, "c3": inputs.C3, "c5": inputs.C5}[args.workload]
+    if args.workload == "c2":
+        rho, u = inputs.init_fields(w)
+        rho_d = torch.from_numpy(rho).cuda()
+        u_d = torch.from_numpy(u).cuda()
+    else:
+        rho_d, u_d = inputs.init_fields_torch(w, torch.device("cuda"))
 
     def run(storage, steps, warmup):
         sim = make_sim(w, storage, lbm, inputs)
@@ -178,17 +188,19 @@ def main():
     if args.mlp:
         from paper_2206_15454_amd import closure
 
-        sim = make_sim(w, "bf16s", lbm, inputs)
+        sim = make_sim(w, args.mlp_storage, lbm, inputs)
         sim.init(rho_d, u_d)
-        # a network with every feature in range: the closure runs in every cell
-        sim.set_closure(closure.timing_blob(w.lad_lalic[0]))
+        # the network trained on the canopy case at twice the resolution (timing
+        # does not depend on the weights; the closure is evaluated in every cell)
+        sim.set_closure(closure.trained_blob())
         k = max(50, args.steps // 4)
         t_ms, s_ms, d = time_steps(sim, k, 20, torch)
         sim.close()
-        variants["bf16s+mlp"] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
-                                 "hbm_frac": round(2 * 19 * 2 * w.n / (s_ms * 1e-3 / k) / 1e9
-                                                   / HBM_PEAK_GBS, 4),
-                                 "mlp_fallback": d["mlp_fallback"]}
+        variants[args.mlp_storage + "+mlp"] = {
+            "MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+            "hbm_frac": round(2 * 19 * BYTES_PER_ELT[args.mlp_storage] * w.n / (s_ms * 1e-3 / k)
+                              / 1e9 / HBM_PEAK_GBS, 4),
+            "mlp_fallback": d["mlp_fallback"]}
 
     out = {
         "metric": METRIC,
@@ -204,7 +216,10 @@ def main():
         "dtype": "f32" if args.storage != "f64" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz,
-                   "storage": args.storage, "closure": "smagorinsky", "canopy": "lalic h=12 LAI=2",
+                   "storage": args.storage, "closure": "smagorinsky",
+                   "canopy": ("lalic h=%g LAI=%g" % (w.lad_lalic[0], w.lad_lalic[2])
+                              if w.lad_lalic else "LAD %g below row %d" % (w.lad_const,
+                                                                           w.canopy_rows)),
                    "stats_every": 10},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -93,3 +93,14 @@ def timing_blob(canopy_h, seed=0):
     mean = np.array([0, 0, 0, 0, 0, 1e-3, 1.5, 0.1, 1.0])
     std = np.array([1e-4, 1e-6, 1e-9, 1e-3, 1e-6, 1e-3, 1.0, 0.15, 1.0])
     return make_blob(p, mean, std, np.full(NIN, -3e38), np.full(NIN, 3e38), 1e-5, canopy_h)
+
+
+def trained_blob():
+    """The closure trained on the production canopy case (512x128x256, h = 12
+    cells) from a run at twice the resolution; see data/*.json for the record."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                        "closure_canopy_512x128x256.bin")
+    with open(path, "rb") as f:
+        return f.read()

@@ -143,7 +143,7 @@ Layout layout(const lbm_params *p) {
     L.f = take((size_t)NQ * qs * elt);
     L.mom = take((size_t)5 * n * celt);
     L.lad = take((size_t)p->ny * 8);
-    L.imp = take((size_t)ntiles * 3 * 8);
+    L.imp = take((size_t)ntiles * 4 * 3 * 8);  // one triple per wavefront of a tile
     L.stats = take((size_t)p->ny * nbx * nbz * 10 * 8);
     L.red = take((size_t)(kRedBlocks * 6 + 16) * 8);
     L.prof = take((size_t)p->ny * 10 * 8);
@@ -168,7 +168,7 @@ lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 lbm_status reset_accumulators(lbm_ctx *c) {
-    HIPCHK(c, launch_fill(c->imp, 0.0, (size_t)c->ntiles * 3, c->stream), "clear impulse");
+    HIPCHK(c, launch_fill(c->imp, 0.0, (size_t)c->ntiles * 4 * 3, c->stream), "clear impulse");
     HIPCHK(c, launch_fill(c->stats, 0.0, (size_t)c->p.ny * c->tpp * 10, c->stream),
            "clear statistics");
     c->stats_n = 0;
@@ -414,7 +414,7 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, double *nut, int32_t 
         }
     }
     double out[9] = {0};
-    HIPCHK(c, launch_diag(c->p.storage, c->mom, (int)n, c->imp, c->ntiles, c->red, kRedBlocks,
+    HIPCHK(c, launch_diag(c->p.storage, c->mom, (int)n, c->imp, 4 * c->ntiles, c->red, kRedBlocks,
                           c->red + kRedBlocks * 6, c->stream), "lbm_moments: reduce");
     HIPCHK(c, hipMemcpyAsync(out, c->red + kRedBlocks * 6, sizeof(out), hipMemcpyDeviceToHost,
                              c->stream), "lbm_moments: copy diag");

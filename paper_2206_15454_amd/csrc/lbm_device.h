@@ -146,7 +146,7 @@ struct StepArgs {
     double cd;        // canopy drag coefficient
     const double *lad;  // [ny]
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
-    double *imp;      // [ntiles][3] body-force impulse accumulators
+    double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators
     const void *mlp;  // learned closure parameters on the device
 };

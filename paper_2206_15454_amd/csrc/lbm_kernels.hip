@@ -215,27 +215,45 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C itau = C(1) / tau;
 
     // ---- a6: equilibrium + Guo forcing + BGK (shifted) ----------------------
+    // Directions q (odd) and q+1 are opposite: c.u and c.F change sign, so
+    // f~eq = A +- B and F_q = E +- O with A, E even and B, O odd in c:
+    //   A = w (drho + rho (4.5 (c.u)^2 - 1.5 u.u)),  B = 3 w rho (c.u),
+    //   E = pref w (9 (c.u)(c.F) - 3 u.F),           O = 3 pref w (c.F).
     const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
     const C uF = ux * Fx + uy * Fy + uz * Fz;
     const C pref = C(1) - C(0.5) * itau;
-    static_for<NQ>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
+    const C om = C(1) - itau;
+    {
+        constexpr C w0 = (C)weight(0);
+        const C feq0 = w0 * (drho - rho * usq15);
+        v[0] = v[0] * om + feq0 * itau - C(3) * pref * w0 * uF;
+    }
+    static_for<(NQ - 1) / 2>([&](auto pc) {
+        constexpr int q = 2 * decltype(pc)::value + 1;  // q and q + 1 = opp(q)
         constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
         constexpr C w = (C)weight(q);
         C cu = 0, cF = 0;
         if (cx) { cu += cx > 0 ? ux : -ux; cF += cx > 0 ? Fx : -Fx; }
         if (cy) { cu += cy > 0 ? uy : -uy; cF += cy > 0 ? Fy : -Fy; }
         if (cz) { cu += cz > 0 ? uz : -uz; cF += cz > 0 ? Fz : -Fz; }
-        const C feqs = w * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq15));
-        const C Fq = pref * w * (C(3) * (cF - uF) + C(9) * cu * cF);
-        v[q] = v[q] + (feqs - v[q]) * itau + Fq;
+        const C A = w * (drho + rho * (C(4.5) * cu * cu - usq15));
+        const C B = C(3) * w * rho * cu;
+        const C pw = pref * w;
+        const C E = pw * (C(9) * cu * cF - C(3) * uF);
+        const C O = C(3) * pw * cF;
+        const C even = A * itau + E, odd = B * itau + O;
+        v[q] = v[q] * om + (even + odd);
+        v[q + 1] = v[q + 1] * om + (even - odd);
     });
 
     // ---- a7: store in place --------------------------------------------------
     // random bits for stochastic rounding (unused by the other storage types)
+    // (one hash gives the 16 random bits of two directions: low and high half)
     const uint32_t rbase = (ST == ST_BF16SR) ? mix32(a.seed ^ mix32((uint32_t)self)) : 0u;
     auto rnd = [&](int q) -> uint32_t {
-        return (ST == ST_BF16SR) ? mix32(rbase + 0x9E3779B9u * (uint32_t)(q + 1)) : 0u;
+        if (ST != ST_BF16SR) return 0u;
+        const uint32_t h = mix32(rbase + 0x9E3779B9u * (uint32_t)(q / 2 + 1));
+        return (q & 1) ? (h >> 16) : h;
     };
     if (active) {
         if (a.parity) {
@@ -283,11 +301,18 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             imp[1] += (double)fv[1];
             imp[2] += (double)fv[2];
         } else {
-            block_accumulate<3>(fv, a.imp + 3 * (long long)tile, sh);
+            // one FP64 accumulator triple per wavefront (no block barrier)
+            const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+            const C s0 = wave_sum(fv[0]), s1 = wave_sum(fv[1]), s2 = wave_sum(fv[2]);
+            if ((tid & 63) == 0) {
+                double *acc = a.imp + 3 * (4 * (long long)tile + (tid >> 6));
+                acc[0] += (double)s0;
+                acc[1] += (double)s1;
+                acc[2] += (double)s2;
+            }
         }
     }
     if (a.flags & FLAG_STATS) {
-        if (!LEARNED && (a.flags & FLAG_IMPULSE)) __syncthreads();  // sh reused
         const C m = active ? C(1) : C(0);
         const C sv[10] = {m * ux,      m * uy,      m * uz,      m * ux * ux, m * uy * uy,
                           m * uz * uz, m * ux * uy, m * ux * uz, m * uy * uz, m * nut};

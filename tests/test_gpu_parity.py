@@ -209,7 +209,10 @@ def test_momentum_balance_periodic_f32():
     g.step(50)
     d1 = g.diag()
     M = d0["mass"]
-    assert d1["mom_x"] - d0["mom_x"] == pytest.approx(50 * M * 1e-5, rel=1e-4)
+    # each step rounds every stored population to FP32 (<= 2^-24 |f~| each,
+    # |f~| <= 0.01 here): the momentum of 4096 cells can move by up to
+    # 4096 * 18 * 2^-24 * 0.01 ~ 4.4e-5 per step if the roundings line up
+    assert abs(d1["mom_x"] - d0["mom_x"] - 50 * M * 1e-5) <= 50 * 4.4e-5
     assert d1["imp_x"] == pytest.approx(51 * M * 1e-5, rel=1e-6)
 
 
@@ -229,7 +232,10 @@ def test_stochastic_rounding_is_unbiased():
         g.step(1)
         so = o.get_f() - W[:, None, None, None]
         sg = g.get_f() - W[:, None, None, None]
-        errs[st] = (sg - so) / ulp(so, st)
+        # only values well above the FP32 arithmetic error of the step (a few
+        # 1e-9 absolute), so that the rounding into BF16 is what is measured
+        big = np.abs(so) > 1e-5
+        errs[st] = ((sg - so) / ulp(so, st))[big]
     e_rn, e_sr = errs["bf16s"], errs["bf16sr"]
     print("signed error in ulps: RN mean %.4f max %.3f; SR mean %.4f max %.3f std %.3f" % (
         e_rn.mean(), np.abs(e_rn).max(), e_sr.mean(), np.abs(e_sr).max(), e_sr.std()))
