@@ -53,10 +53,21 @@ def measured_traffic(storage, cells):
     return ent.get("bytes_per_launch")
 
 
+def workload_lad(w, lad_fn, inputs):
+    """LAD per row from a workload, with the given Eq. (af_theory) routine"""
+    if w.lad_lalic is not None:
+        h, ym, lai = w.lad_lalic
+        return lad_fn(h, ym, w.ny, lai=lai)
+    if w.lad_profile is not None:
+        h, ym, afm = w.lad_profile
+        return lad_fn(h, ym, w.ny, afm=afm)
+    return inputs.lad_constant(w)
+
+
 def make_sim(w, storage, lbm, inputs):
-    lad = lbm.lad_lalic(*w.lad_lalic[:2], w.ny, lai=w.lad_lalic[2]) \
-        if w.lad_lalic is not None else inputs.lad_constant(w)
-    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    lad = workload_lad(w, lbm.lad_lalic, inputs)
+    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                  u_wall=w.u_wall)
     sim.set_canopy(w.cd, lad)
     return sim
 
@@ -90,12 +101,9 @@ def cpu_baseline(w, target_s=10.0):
 
     nz = max(1, min(w.nz, 16))
     ws = inputs.scaled(w, w.nx, w.ny, nz)
-    if w.lad_lalic is not None:
-        h, ym, lai = w.lad_lalic
-        lad = ref.lad_lalic(h, ym, w.ny, lai=lai)
-    else:
-        lad = inputs.lad_constant(w)
+    lad = workload_lad(w, ref.lad_lalic, inputs)
     sim = ref.RefLBM(ws.nx, ws.ny, ws.nz, ws.tau0, ws.c_smag, ws.g, ws.bc_lo, ws.bc_hi)
+    sim.set_wall_velocity(w.u_wall)
     sim.set_canopy(ws.cd, lad)
     rho, u = inputs.init_fields(ws)
     sim.init(rho, u)
@@ -128,9 +136,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c5", "abl1", "abl2", "abl3", "channel"],
                     help="c2: production canopy 512x128x256 (default); c3/c5: 1024x256x512 "
-                         "with the 64x32x32 case's physics (profiling)")
+                         "with the 64x32x32 case's physics; abl1-3: the paper's ABL fine mesh "
+                         "350x140x280 with LAD cases 1-3; channel: the paper's Re_tau=180 "
+                         "channel 372x62x124")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,7 +166,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel(), "copy_bytes_written": y.numel(),
                           "launches": 3}), flush=True)
         return
-    w = {"c2": inputs.C2, "c3": inputs.C3, "c5": inputs.C5}[args.workload]
+    w = {"c2": inputs.C2, "c3": inputs.C3, "c5": inputs.C5, "abl1": inputs.ABL1,
+         "abl2": inputs.ABL2, "abl3": inputs.ABL3, "channel": inputs.CHANNEL}[args.workload]
     if args.workload == "c2":
         rho, u = inputs.init_fields(w)
         rho_d = torch.from_numpy(rho).cuda()
@@ -218,8 +230,10 @@ def main():
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz,
                    "storage": args.storage, "closure": "smagorinsky",
                    "canopy": ("lalic h=%g LAI=%g" % (w.lad_lalic[0], w.lad_lalic[2])
-                              if w.lad_lalic else "LAD %g below row %d" % (w.lad_const,
-                                                                           w.canopy_rows)),
+                              if w.lad_lalic else
+                              "lalic h=%g a_fm=%g" % (w.lad_profile[0], w.lad_profile[2])
+                              if w.lad_profile else
+                              "LAD %g below row %d" % (w.lad_const, w.canopy_rows)),
                    "stats_every": 10},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -57,9 +57,17 @@ typedef enum {
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_BF16SR = 4 } lbm_storage;
 
 /* Wall-normal (y) boundaries.  BOUNCEBACK is the halfway no-slip wall;
- * FREESLIP is specular reflection (a symmetry plane); PERIODIC must be set
- * on both ends or neither. */
-typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_FREESLIP = 2 } lbm_bc;
+ * FREESLIP is specular reflection (a symmetry plane); EQUILIBRIUM is the
+ * forced-equilibrium boundary of Sec. 5.1 (the upper boundary "moves with the
+ * free-stream velocity"): every population entering through it is
+ * feq(1, u_wall), populations leaving through it are lost; PERIODIC must be
+ * set on both ends or neither. */
+typedef enum {
+    LBM_BC_PERIODIC = 0,
+    LBM_BC_BOUNCEBACK = 1,
+    LBM_BC_FREESLIP = 2,
+    LBM_BC_EQUILIBRIUM = 3
+} lbm_bc;
 
 typedef enum { LBM_CLOSURE_SMAG = 0, LBM_CLOSURE_MLP = 1 } lbm_closure;
 
@@ -72,6 +80,7 @@ typedef struct lbm_params {
     int32_t bc_ylo;      /* lbm_bc at y = 0  */
     int32_t bc_yhi;      /* lbm_bc at y = ny */
     void *stream;        /* hipStream_t to enqueue on; NULL = the null stream */
+    double u_wall[3];    /* velocity of an LBM_BC_EQUILIBRIUM boundary (finite) */
 } lbm_params;
 
 typedef struct lbm_diag {

@@ -48,6 +48,9 @@
  *       u, calculate the forest force, correct u).  No iteration.
  *   R9  Walls: halfway bounce-back (no-slip, wall half a cell below the first
  *       cell centre); free-slip is specular reflection; x and z periodic.
+ *       The forced-equilibrium boundary of Sec. 5.1 ("moves with the free-
+ *       stream velocity") supplies f_eq(1, u_wall) for every population
+ *       entering from it; populations leaving through it are lost.
  *   R10 The LAD is evaluated at cell centres y_j = j + 1/2; n = 6 below y_m,
  *       1/2 from y_m to h; zero at and above h.
  *   R11 Initial state: f* = feq(rho0, u0), taken as post-collision at t = 0.
@@ -100,7 +103,7 @@ static int mirror_y(int q) {
     return -1;
 }
 
-enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2 };
+enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2, BC_EQUILIBRIUM = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* pure per-cell formulas                                                    */
@@ -218,6 +221,7 @@ typedef struct {
     size_t n;
     double tau0, csmag, g[3];
     int bc_lo, bc_hi;
+    double u_wall[3]; /* velocity of the forced-equilibrium boundary (density 1) */
     double cd;
     double *lad;
     int vector_drag;
@@ -242,7 +246,7 @@ static int wrap(int a, int n) { return ((a % n) + n) % n; }
 void *ref_create(int nx, int ny, int nz, double tau0, double csmag, double gx, double gy,
                  double gz, int bc_lo, int bc_hi) {
     if (nx < 1 || ny < 1 || nz < 1 || !(tau0 > 0.5) || csmag < 0.0) return NULL;
-    if (bc_lo < 0 || bc_lo > 2 || bc_hi < 0 || bc_hi > 2) return NULL;
+    if (bc_lo < 0 || bc_lo > 3 || bc_hi < 0 || bc_hi > 3) return NULL;
     if ((bc_lo == BC_PERIODIC) != (bc_hi == BC_PERIODIC)) return NULL;
     ref_ctx *c = (ref_ctx *)calloc(1, sizeof(ref_ctx));
     c->nx = nx; c->ny = ny; c->nz = nz;
@@ -286,6 +290,15 @@ double ref_mlp_canopy_h(const void *m);
 
 /* learned closure (NULL restores Smagorinsky); the blob fixes the canopy
  * height used by the y/h feature */
+/* velocity imposed by a forced-equilibrium boundary (Sec. 5.1: the upper
+ * boundary moves with the free-stream velocity) */
+void ref_set_wall_velocity(void *h, double ux, double uy, double uz) {
+    ref_ctx *c = (ref_ctx *)h;
+    c->u_wall[0] = ux;
+    c->u_wall[1] = uy;
+    c->u_wall[2] = uz;
+}
+
 void ref_set_closure(void *h, const void *mlp) {
     ref_ctx *c = (ref_ctx *)h;
     c->mlp = (const struct mlp_ref *)mlp;
@@ -336,6 +349,11 @@ static double pull(const ref_ctx *c, const double *fp, int q, int i, int j, int 
         return fp[q * n + cell(c, si, wrap(sj, c->ny), sk)];
     case BC_BOUNCEBACK: /* the population that left this cell towards the wall */
         return fp[opposite(q) * n + cell(c, i, j, k)];
+    case BC_EQUILIBRIUM: { /* forced equilibrium at the wall velocity, density 1 */
+        double feq[NQ];
+        ref_feq(1.0, c->u_wall, feq);
+        return feq[q];
+    }
     default: /* free-slip: left the wall row of the upstream column moving towards the wall */
         return fp[mirror_y(q) * n + cell(c, si, wall_row, sk)];
     }

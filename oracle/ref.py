@@ -13,7 +13,7 @@ from . import build as _build
 
 _LIB = None
 
-BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP = 0, 1, 2
+BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP, BC_EQUILIBRIUM = 0, 1, 2, 3
 DIAG_KEYS = ("mass", "mom_x", "mom_y", "mom_z", "imp_x", "imp_y", "imp_z", "max_u", "t",
              "nonfinite", "mlp_fallback")
 
@@ -42,6 +42,7 @@ def lib():
         L.ref_moments.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.ref_stats.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, C.POINTER(C.c_int64)]
         L.ref_set_closure.argtypes = [C.c_void_p, C.c_void_p]
+        L.ref_set_wall_velocity.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.ref_lattice.argtypes = [C.POINTER(C.c_int), _dp]
         L.ref_feq.argtypes = [C.c_double, _dp, _dp]
         L.ref_guo.argtypes = [C.c_double, _dp, _dp, _dp]
@@ -218,6 +219,9 @@ class RefLBM:
         lad = np.ascontiguousarray(lad, dtype=np.float64)
         if lib().ref_set_canopy(self.h, float(cd), _ptr(lad), lad.size, int(vector_drag)) != 0:
             raise ValueError("lad length must equal ny")
+
+    def set_wall_velocity(self, u):
+        lib().ref_set_wall_velocity(self.h, float(u[0]), float(u[1]), float(u[2]))
 
     def set_closure(self, mlp):
         self._mlp = mlp

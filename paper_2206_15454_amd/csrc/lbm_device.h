@@ -32,7 +32,7 @@ constexpr double weight(int q) {
     return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2 };
+enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_FREESLIP = 2, BC_EQUILIBRIUM = 3 };
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3, ST_BF16SR = 4 };
 
 // step flags
@@ -143,6 +143,7 @@ struct StepArgs {
     double tau0;      // molecular relaxation time
     double ksmag;     // 18 sqrt(2) C_smag
     double g[3];      // driving acceleration
+    double u_wall[3]; // velocity of a forced-equilibrium boundary (density 1)
     double cd;        // canopy drag coefficient
     const double *lad;  // [ny]
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
@@ -177,7 +178,7 @@ hipError_t launch_init(int storage, void *f, long long qs, void *mom, const doub
 hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
                         hipStream_t s);
 hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
-                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);
+                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);  // EQ stores like BB
 hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
                               double *nut, int n, hipStream_t s);
 hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, int nimp,

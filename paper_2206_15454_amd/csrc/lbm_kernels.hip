@@ -94,11 +94,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const long long qs = a.qs;
 
     // ---- a1/a2: stream in (AA slot map with walls), decode ----------------
+    // a forced-equilibrium boundary supplies feq(1, u_wall) - w for every
+    // population entering through it (both parities)
+    auto feq_wall = [&](int q) -> C {
+        const C uwx = (C)a.u_wall[0], uwy = (C)a.u_wall[1], uwz = (C)a.u_wall[2];
+        const C cu = (C)CX[q] * uwx + (C)CY[q] * uwy + (C)CZ[q] * uwz;
+        const C uu = uwx * uwx + uwy * uwy + uwz * uwz;
+        return (C)weight(q) * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
+    };
+    auto from_eq_wall = [&](int cy) -> bool {  // uniform per block
+        const int js = j - cy;
+        return cy != 0 && (js < 0 || js >= ny) && (js < 0 ? a.bc_lo : a.bc_hi) == BC_EQUILIBRIUM;
+    };
     C v[NQ];
     if (a.parity) {
         static_for<NQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            v[q] = CD::ld(f + q * qs + self);
+            if (from_eq_wall(CY[q]))
+                v[q] = feq_wall(q);
+            else
+                v[q] = CD::ld(f + q * qs + self);
         });
     } else {
         static_for<NQ>([&](auto qc) {
@@ -107,7 +122,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             const int js = j - cy;
             if (cy != 0 && (js < 0 || js >= ny) &&
                 (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
-                if ((js < 0 ? a.bc_lo : a.bc_hi) == BC_BOUNCEBACK)
+                const int bc = js < 0 ? a.bc_lo : a.bc_hi;
+                if (bc == BC_EQUILIBRIUM)
+                    v[q] = feq_wall(q);
+                else if (bc == BC_BOUNCEBACK)
                     v[q] = CD::ld(f + q * qs + self);  // left this cell towards the wall
                 else  // free slip: left the wall row upstream, moving towards the wall
                     v[q] = CD::ld(f + opp(mir(q)) * qs + cell(-cx, 0, -cz));
@@ -268,7 +286,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                 const int jt = j + cy;
                 if (cy != 0 && (jt < 0 || jt >= ny) &&
                     (jt < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
-                    if ((jt < 0 ? a.bc_lo : a.bc_hi) == BC_BOUNCEBACK)
+                    // bounce-back, and the forced-equilibrium boundary, keep the
+                    // leaving population in the own cell's opposite slot (a
+                    // forced-equilibrium boundary never reads it back)
+                    if ((jt < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
                         CD::st(f + opp(q) * qs + self, v[q], rnd(q));
                     else
                         CD::st(f + mir(q) * qs + cell(cx, 0, cz), v[q], rnd(q));
@@ -436,7 +457,7 @@ __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs
             const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
             const int jt = j + cy;
             if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
-                if ((jt < 0 ? bc_lo : bc_hi) == BC_BOUNCEBACK) {
+                if ((jt < 0 ? bc_lo : bc_hi) != BC_FREESLIP) {  // bounce-back or equilibrium
                     slot = opp(q);
                     src = x;
                 } else {

@@ -12,15 +12,16 @@ array of shape (3, nz, ny, nx) in C order; y_j = j + 1/2; rho = 1 exactly.
 
 Leaf-area density: a workload names either a constant value below a canopy
 row (``lad_const``, ``canopy_rows``) or the Lalic-Mihailovic profile by its
-parameters (``lad_lalic``: h, y_m, LAI); the caller evaluates the profile with
-its own implementation of the paper's Eq. (af_theory).
+parameters (``lad_lalic``: h, y_m, LAI normalisation; ``lad_profile``: h,
+y_m, peak a_fm); the caller evaluates the profile with its own
+implementation of the paper's Eq. (af_theory).
 """
 from dataclasses import dataclass, field, replace
 from typing import Optional, Tuple
 
 import numpy as np
 
-BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP = 0, 1, 2
+BC_PERIODIC, BC_BOUNCEBACK, BC_FREESLIP, BC_EQUILIBRIUM = 0, 1, 2, 3
 STORAGES = ("f64", "f32", "f16s", "bf16s", "bf16sr")
 
 
@@ -45,6 +46,9 @@ class Workload:
     noise: float = 0.02
     seed: int = 1
     steps: int = 200
+    u_wall: Tuple[float, float, float] = (0.0, 0.0, 0.0)  # forced-equilibrium boundary
+    lad_profile: Optional[Tuple[float, float, float]] = None  # (h, y_m, a_fm): Eq. af_theory peak
+    channel: bool = False  # initial profile mirrored about the mid-plane (two walls)
     extra: dict = field(default_factory=dict, compare=False, hash=False)
 
     @property
@@ -85,7 +89,35 @@ C4 = replace(C2, name="canopy-abl-fine-1024x256x512-f32", nx=1024, ny=256, nz=51
 C5 = replace(C3, name="canopy-abl-1024x256x512-bf16s-mlp", storage="bf16s", seed=3,
              steps=20000)
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5)}
+# The paper's ABL over a homogeneous forest (Sec. 5), fine mesh 350x140x280 of
+# 1000x400x800 m (dx = 2.857 m): forest height h = 20 m = 7 cells, C_D = 0.15,
+# bounce-back ground, forced-equilibrium top moving with the free stream
+# (U = 0.08), periodic x and z.  LAD per cell = a_f [1/m] * dx:
+#   case 1: constant 0.215/m -> 0.6143; case 2: Eq. (af_theory) with
+#   y_m = 0.7 h, a_fm = 0.38/m -> peak 1.0857; case 3: no forest.
+# The driving force of the paper cannot be recovered from its text; here
+# g = u*^2 / Ny with u* = U/20.
+_DX_ABL = 1000.0 / 350.0
+ABL1 = Workload(name="paper-abl-350x140x280-case1", nx=350, ny=140, nz=280, storage="f32",
+                tau0=0.5005, c_smag=0.01, g=((0.08 / 20) ** 2 / 140, 0.0, 0.0),
+                bc_lo=BC_BOUNCEBACK, bc_hi=BC_EQUILIBRIUM, cd=0.15,
+                lad_const=0.215 * _DX_ABL, canopy_rows=7, u_ref=0.08, y_ref=140.0, noise=0.05,
+                seed=5, steps=20000, u_wall=(0.08, 0.0, 0.0))
+ABL2 = replace(ABL1, name="paper-abl-350x140x280-case2",
+               lad_profile=(7.0, 0.7 * 7.0, 0.38 * _DX_ABL))
+ABL3 = replace(ABL1, name="paper-abl-350x140x280-case3", lad_const=0.0, canopy_rows=0)
+
+# The paper's validation channel (Sec. 4, Re_tau = 180): 12 x 2 x 4 H at 31
+# cells per H -> 372 x 62 x 124, walls top and bottom; dx = 1/31, dt = 0.001,
+# nu = 1/3250, F = 0.002986 in lattice units: tau0 = 0.5 + 3 nu dt/dx^2,
+# g = F dt^2/dx.
+CHANNEL = Workload(name="paper-channel-372x62x124", nx=372, ny=62, nz=124, storage="f32",
+                   tau0=0.5 + 3.0 * (1.0 / 3250.0) * 0.001 * 31.0 ** 2, c_smag=0.01,
+                   g=(0.002986 * 0.001 ** 2 * 31.0, 0.0, 0.0), bc_lo=BC_BOUNCEBACK,
+                   bc_hi=BC_BOUNCEBACK, cd=0.0, u_ref=0.03, y_ref=31.0, noise=0.05, seed=6,
+                   steps=20000, channel=True)
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL)}
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
@@ -94,8 +126,8 @@ def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
 
 
 def lad_constant(w: Workload) -> Optional[np.ndarray]:
-    """Constant-LAD canopy rows (None when the workload uses the profile)."""
-    if w.lad_lalic is not None:
+    """Constant-LAD canopy rows (None when the workload uses a profile)."""
+    if w.lad_lalic is not None or w.lad_profile is not None:
         return None
     lad = np.zeros(w.ny)
     lad[: min(w.canopy_rows, w.ny)] = w.lad_const
@@ -108,6 +140,8 @@ def init_fields(w: Workload, seed: Optional[int] = None):
     rng = np.random.default_rng(w.seed if seed is None else seed)
     xi = rng.uniform(-1.0, 1.0, size=(3,) + w.shape)
     y = np.arange(w.ny, dtype=np.float64) + 0.5
+    if w.channel:
+        y = np.minimum(y, w.ny - y)
     ubar = w.u_ref * (y / w.y_ref) ** (1.0 / 7.0)
     u = w.noise * w.u_ref * xi
     u[0] += ubar[None, :, None]
@@ -127,6 +161,8 @@ def init_fields_torch(w: Workload, device, seed: Optional[int] = None):
     u = torch.rand((3,) + w.shape, generator=gen, device=device, dtype=torch.float64)
     u.mul_(2.0).sub_(1.0).mul_(w.noise * w.u_ref)
     y = torch.arange(w.ny, device=device, dtype=torch.float64) + 0.5
+    if w.channel:
+        y = torch.minimum(y, w.ny - y)
     u[0] += (w.u_ref * (y / w.y_ref) ** (1.0 / 7.0))[None, :, None]
     rho = torch.ones(w.shape, device=device, dtype=torch.float64)
     return rho, u

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBMX_LIB") or os.path.join(_HERE, "liblbmx.so")
 
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "bf16sr": 4}
-BC = {"periodic": 0, "bounceback": 1, "freeslip": 2}
+BC = {"periodic": 0, "bounceback": 1, "freeslip": 2, "equilibrium": 3}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSTABLE"}
 
 
@@ -28,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("storage", C.c_int32), ("tau0", C.c_double), ("c_smag", C.c_double),
                 ("g", C.c_double * 3), ("bc_ylo", C.c_int32), ("bc_yhi", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("u_wall", C.c_double * 3)]
 
 
 class Diag(C.Structure):
@@ -137,7 +137,7 @@ class LBM:
     """One simulation context on the current GPU."""
 
     def __init__(self, nx, ny, nz, storage="f32", tau0=0.52, c_smag=0.01, g=(0.0, 0.0, 0.0),
-                 bc_lo="bounceback", bc_hi="freeslip", stream=None):
+                 bc_lo="bounceback", bc_hi="freeslip", stream=None, u_wall=(0.0, 0.0, 0.0)):
         import torch
 
         self.torch = torch
@@ -147,7 +147,8 @@ class LBM:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.p = Params(nx, ny, nz, STORAGE[storage], float(tau0), float(c_smag),
                         (C.c_double * 3)(*map(float, g)), bc_lo, bc_hi,
-                        C.c_void_p(self.stream.cuda_stream))
+                        C.c_void_p(self.stream.cuda_stream),
+                        (C.c_double * 3)(*map(float, u_wall)))
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
         self.storage = storage

@@ -35,11 +35,15 @@ def _lad(w):
     if w.lad_lalic is not None:
         h, ym, lai = w.lad_lalic
         return lbm.lad_lalic(h, ym, w.ny, lai=lai)
+    if w.lad_profile is not None:
+        h, ym, afm = w.lad_profile
+        return lbm.lad_lalic(h, ym, w.ny, afm=afm)
     return inputs.lad_constant(w)
 
 
 def make(w, storage, rho, u, blob=None):
-    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                  u_wall=w.u_wall)
     sim.set_canopy(w.cd, _lad(w))
     sim.init(rho, u)
     if blob is not None:

@@ -20,9 +20,12 @@ def require_gpu():
 
 def oracle_lad(w):
     lad = inputs.lad_constant(w)
-    if lad is None:
+    if lad is None and w.lad_lalic is not None:
         h, ym, lai = w.lad_lalic
         lad = ref.lad_lalic(h, ym, w.ny, lai=lai)
+    elif lad is None:
+        h, ym, afm = w.lad_profile
+        lad = ref.lad_lalic(h, ym, w.ny, afm=afm)
     return lad
 
 
@@ -32,7 +35,9 @@ def make_pair(w, storage=None, seed=None, init=True, vector_drag=False):
 
     storage = storage or w.storage
     o = ref.RefLBM(w.nx, w.ny, w.nz, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
-    g = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    o.set_wall_velocity(w.u_wall)
+    g = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                u_wall=w.u_wall)
     lad = oracle_lad(w)
     o.set_canopy(w.cd, lad, vector_drag)
     g.set_canopy(w.cd, lad, vector_drag)
@@ -73,3 +78,13 @@ def ulp(x, storage):
             "bf16sr": 2.0 ** -126}[storage]
     e = np.floor(np.log2(np.maximum(a, tiny)))
     return 2.0 ** (e - mant)
+
+
+def make_gpu(w, storage=None):
+    """GPU simulation of workload w (no oracle), canopy set, not initialised."""
+    from paper_2206_15454_amd import lbm
+
+    g = lbm.LBM(w.nx, w.ny, w.nz, storage or w.storage, w.tau0, w.c_smag, w.g, w.bc_lo,
+                w.bc_hi, u_wall=w.u_wall)
+    g.set_canopy(w.cd, oracle_lad(w))
+    return g

@@ -69,11 +69,14 @@ def test_parameter_validation_without_device(lbm):
         d = dict(nx=8, ny=4, nz=4, storage=1, tau0=0.6, c_smag=0.01, bc_ylo=1, bc_yhi=2)
         d.update(kw)
         return lbm.Params(d["nx"], d["ny"], d["nz"], d["storage"], d["tau0"], d["c_smag"],
-                          (C.c_double * 3)(0, 0, 0), d["bc_ylo"], d["bc_yhi"], None)
+                          (C.c_double * 3)(0, 0, 0), d["bc_ylo"], d["bc_yhi"], None,
+                          (C.c_double * 3)(d.get("uw", 0.0), 0, 0))
 
     assert L.lbm_required_bytes(C.byref(P())) > 19 * 8 * 4 * 4 * 4
+    assert L.lbm_required_bytes(C.byref(P(bc_yhi=3, uw=0.1))) > 0  # forced equilibrium
     for bad in (dict(tau0=0.5), dict(nx=0), dict(storage=7), dict(bc_ylo=0),
-                dict(c_smag=-1.0), dict(bc_yhi=5), dict(nx=2048, ny=1024, nz=1024)):
+                dict(c_smag=-1.0), dict(bc_yhi=5), dict(nx=2048, ny=1024, nz=1024),
+                dict(uw=float("nan"))):
         assert L.lbm_required_bytes(C.byref(P(**bad))) == 0, bad
         h = C.c_void_p()
         assert L.lbm_create(C.byref(P(**bad)), None, 0, C.byref(h)) == 1

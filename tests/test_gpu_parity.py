@@ -57,11 +57,15 @@ def test_f64_canopy_200_steps_matches_oracle():
     ((64, 6, 4), (0, 0)),     # fully periodic
     ((300, 3, 2), (2, 1)),    # several x tiles with a ragged tail
     ((8, 1, 9), (1, 2)),      # a single row between the walls
+    ((40, 6, 5), (1, 3)),     # forced-equilibrium top (the paper's ABL top)
+    ((33, 4, 3), (3, 3)),     # forced equilibrium at both ends
+    ((20, 1, 4), (2, 3)),     # one row: free slip below, equilibrium above
 ])
 def test_f64_boundaries_and_ragged_grids(shape, bcs):
     nx, ny, nz = shape
     w = inputs.scaled(inputs.C1, nx, ny, nz, bc_lo=bcs[0], bc_hi=bcs[1],
-                      canopy_rows=max(1, ny // 2), g=(2e-5, 1e-6, -3e-6))
+                      canopy_rows=max(1, ny // 2), g=(2e-5, 1e-6, -3e-6),
+                      u_wall=(0.06, 0.0, 0.01))
     o, g = make_pair(w, seed=17, vector_drag=(nx % 2 == 1))
     o.step(25)
     g.step(25)

@@ -429,3 +429,38 @@ def test_thread_count_does_not_change_results():
             subprocess.run([sys.executable, "-c", code, path], check=True, env=env)
             outs.append(np.load(path))
     assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# forced-equilibrium boundary (Sec. 5.1: the top moves with the free stream)
+# ---------------------------------------------------------------------------
+
+def test_equilibrium_boundary_keeps_a_uniform_stream():
+    """feq(1, U) everywhere is a fixed point when the boundary imposes U."""
+    U = (0.05, 0.0, -0.02)
+    sim = ref.RefLBM(6, 5, 4, tau0=0.6, csmag=0.01, bc_lo=ref.BC_FREESLIP,
+                     bc_hi=ref.BC_EQUILIBRIUM)
+    sim.set_wall_velocity(U)
+    u = np.zeros((3, 4, 5, 6))
+    u[0], u[2] = U[0], U[2]
+    sim.init(np.ones((4, 5, 6)), u)
+    f0 = sim.get_f()
+    sim.step(20)
+    np.testing.assert_allclose(sim.get_f(), f0, rtol=0, atol=20 * 4e-16)  # a few ulps per step
+
+
+def test_equilibrium_boundary_couette_is_linear():
+    """Bounce-back bottom, forced equilibrium at U on top, no force: the
+    steady profile is a straight line from ~0 at the wall to ~U at the top."""
+    H, U = 12, 0.02
+    for tau in (0.6, 0.9):
+        sim = ref.RefLBM(1, H, 1, tau0=tau, csmag=0.0, bc_lo=BB, bc_hi=ref.BC_EQUILIBRIUM)
+        sim.set_wall_velocity((U, 0.0, 0.0))
+        sim.init(np.ones((1, H, 1)), np.zeros((3, 1, H, 1)))
+        sim.step(int(20 * H * H / ((tau - 0.5) / 3)))
+        _, u, _, _ = sim.moments()
+        ux = u[0, 0, :, 0]
+        y = np.arange(H) + 0.5
+        a, b = np.polyfit(y, ux, 1)
+        assert np.max(np.abs(ux - (a * y + b))) <= 1e-10 * U
+        assert abs(b) <= 0.05 * U and 0.8 * U / H <= a <= 1.2 * U / H
