@@ -7,7 +7,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lbm_ref.c", "mlp_ref.c"]
+SOURCES = ["lbm_ref.c", "mlp_ref.c", "forest_ref.c"]
 LIB = os.path.join(HERE, "liblbm_ref.so")
 
 

@@ -224,6 +224,7 @@ typedef struct {
     double u_wall[3]; /* velocity of the forced-equilibrium boundary (density 1) */
     double cd;
     double *lad;
+    double *lad_cell; /* [nz][ny][nx] LAD of a heterogeneous forest, or NULL */
     int vector_drag;
     double canopy_h; /* canopy height in cells, used only by the learned closure's y/h feature */
     double *fa, *fb; /* post-collision populations [q][z][y][x] */
@@ -274,7 +275,7 @@ void ref_destroy(void *h) {
     ref_ctx *c = (ref_ctx *)h;
     if (!c) return;
     free(c->lad); free(c->fa); free(c->fb); free(c->rho); free(c->u); free(c->nut);
-    free(c->stats); free(c);
+    free(c->stats); free(c->lad_cell); free(c);
 }
 
 int ref_set_canopy(void *h, double cd, const double *lad, int ny, int vector_drag) {
@@ -282,6 +283,26 @@ int ref_set_canopy(void *h, double cd, const double *lad, int ny, int vector_dra
     if (ny != c->ny) return 1;
     c->cd = cd;
     for (int j = 0; j < ny; ++j) c->lad[j] = lad ? lad[j] : 0.0;
+    c->vector_drag = vector_drag;
+    free(c->lad_cell);
+    c->lad_cell = NULL;
+    return 0;
+}
+
+double ref_forest_lad(uint32_t code, double afm, int constant);
+
+/* Heterogeneous forest (Sec. 3, Algorithm 2): the LAD of every cell from
+ * its forest code (forest_ref.c); replaces the per-row profile until the
+ * next ref_set_canopy. */
+int ref_set_forest(void *h, double cd, double afm, int constant, const uint32_t *codes,
+                   int vector_drag) {
+    ref_ctx *c = (ref_ctx *)h;
+    double *l = (double *)malloc(c->n * sizeof(double));
+    if (!l) return 1;
+    for (size_t x = 0; x < c->n; ++x) l[x] = ref_forest_lad(codes[x], afm, constant);
+    free(c->lad_cell);
+    c->lad_cell = l;
+    c->cd = cd;
     c->vector_drag = vector_drag;
     return 0;
 }
@@ -371,7 +392,7 @@ void ref_pull(const void *h, double *fin) {
 
 /* One cell of one step in the order of Algorithm 1.  fin: streamed
  * populations; writes post-collision fout, moments, the body force. */
-static void collide_cell(const ref_ctx *c, int jrow, const double *fin, double *fout,
+static void collide_cell(const ref_ctx *c, int jrow, size_t xc, const double *fin, double *fout,
                          double *rho_o, double *u_o, double *nut_o, double *F_o,
                          int *fallback) {
     double rho, jm[3], Pi[9];
@@ -384,7 +405,7 @@ static void collide_cell(const ref_ctx *c, int jrow, const double *fin, double *
         us[a] = (jm[a] + 0.5 * F[a]) / rho;
         u[a] = us[a];
     }
-    double lad = c->lad[jrow];
+    double lad = c->lad_cell ? c->lad_cell[xc] : c->lad[jrow];
     if (lad > 0.0) { /* "if cell x is forest" */
         /* "Calculate forest force", Eq. (forestForce) as an acceleration (R3, R7) */
         double speed = sqrt(us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
@@ -462,8 +483,8 @@ int ref_step(void *h, int64_t nsteps) {
                 for (int i = 0; i < c->nx; ++i) {
                     double fin[NQ], fout[NQ], uo[3], Fo[3], r, nt;
                     for (int q = 0; q < NQ; ++q) fin[q] = pull(c, c->fa, q, i, j, k);
-                    collide_cell(c, j, fin, fout, &r, uo, &nt, Fo, &fb);
                     size_t x = cell(c, i, j, k);
+                    collide_cell(c, j, x, fin, fout, &r, uo, &nt, Fo, &fb);
                     for (int q = 0; q < NQ; ++q) c->fb[q * n + x] = fout[q];
                     c->rho[x] = r;
                     for (int a = 0; a < 3; ++a) {

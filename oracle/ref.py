@@ -64,6 +64,13 @@ def lib():
         L.ref_softplus.restype = C.c_double
         L.ref_softplus.argtypes = [C.c_double]
         L.ref_threads.restype = C.c_int
+        L.ref_forest_codes.argtypes = [_dp, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double,
+                                       C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+        L.ref_forest_lad.restype = C.c_double
+        L.ref_forest_lad.argtypes = [C.c_uint32, C.c_double, C.c_int]
+        L.ref_forest_decode.argtypes = [C.c_uint32] + [C.POINTER(C.c_int)] * 3
+        L.ref_set_forest.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int,
+                                     C.POINTER(C.c_uint32), C.c_int]
         _LIB = L
     return _LIB
 
@@ -116,6 +123,29 @@ def lad_lalic(h, ym, ny, afm=1.0, lai=0.0):
     if rc != 0:
         raise ValueError("invalid LAD parameters")
     return out
+
+
+def forest_codes(points, nx, ny, nz, ym_frac=0.7):
+    """(codes uint32 [nz][ny][nx], number of forest objects) from a point
+    cloud [npts][3] in cell units."""
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    codes = np.zeros((nz, ny, nx), dtype=np.uint32)
+    nobj = C.c_int64(0)
+    rc = lib().ref_forest_codes(_ptr(p), p.shape[0], nx, ny, nz, float(ym_frac),
+                                codes.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(nobj))
+    if rc != 0:
+        raise ValueError("invalid point cloud or y_m fraction")
+    return codes, nobj.value
+
+
+def forest_decode(code):
+    h, y, q = C.c_int(), C.c_int(), C.c_int()
+    lib().ref_forest_decode(int(code), C.byref(h), C.byref(y), C.byref(q))
+    return h.value, y.value, q.value
+
+
+def forest_lad(code, afm, constant=False):
+    return lib().ref_forest_lad(int(code), float(afm), int(constant))
 
 
 def gelu(x):
@@ -219,6 +249,13 @@ class RefLBM:
         lad = np.ascontiguousarray(lad, dtype=np.float64)
         if lib().ref_set_canopy(self.h, float(cd), _ptr(lad), lad.size, int(vector_drag)) != 0:
             raise ValueError("lad length must equal ny")
+
+    def set_forest(self, cd, afm, codes, constant=False, vector_drag=False):
+        codes = np.ascontiguousarray(codes, dtype=np.uint32).reshape(self.shape)
+        if lib().ref_set_forest(self.h, float(cd), float(afm), int(constant),
+                                codes.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                int(vector_drag)) != 0:
+            raise MemoryError("oracle forest")
 
     def set_wall_velocity(self, u):
         lib().ref_set_wall_velocity(self.h, float(u[0]), float(u[1]), float(u[2]))
