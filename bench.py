@@ -38,17 +38,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, cells):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    only if it was taken on the current kernel source."""
+def measured_traffic(storage, w):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, only if it was taken on the current kernel source and
+    the same workload."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    ent = rec.get(storage)
-    if not ent or ent.get("kernel_hash") != kernel_hash() or ent.get("cells") != cells:
+    ent = rec.get("entries", {}).get(f"{w.name}/{storage}")
+    if not ent or ent.get("kernel_hash") != kernel_hash() or ent.get("cells") != w.n:
         return None
     return ent.get("bytes_per_launch")
 
@@ -64,11 +65,25 @@ def workload_lad(w, lad_fn, inputs):
     return inputs.lad_constant(w)
 
 
+_FOREST_CODES = {}
+
+
+def forest_codes(w, lbm, inputs):
+    """Per-cell forest codes of a heterogeneous-forest workload (the library's
+    routine on the workload's seeded point cloud), built once per workload."""
+    if w.name not in _FOREST_CODES:
+        pts = inputs.forest_points(w)
+        _FOREST_CODES[w.name] = lbm.forest_codes(pts, w.nx, w.ny, w.nz, w.forest[4])[0]
+    return _FOREST_CODES[w.name]
+
+
 def make_sim(w, storage, lbm, inputs):
-    lad = workload_lad(w, lbm.lad_lalic, inputs)
     sim = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
-                  u_wall=w.u_wall)
-    sim.set_canopy(w.cd, lad)
+                  u_wall=w.u_wall, forest_map=w.forest is not None)
+    if w.forest is not None:
+        sim.set_forest(w.cd, w.forest[3], forest_codes(w, lbm, inputs))
+        return sim
+    sim.set_canopy(w.cd, workload_lad(w, lbm.lad_lalic, inputs))
     return sim
 
 
@@ -101,10 +116,14 @@ def cpu_baseline(w, target_s=10.0):
 
     nz = max(1, min(w.nz, 16))
     ws = inputs.scaled(w, w.nx, w.ny, nz)
-    lad = workload_lad(w, ref.lad_lalic, inputs)
     sim = ref.RefLBM(ws.nx, ws.ny, ws.nz, ws.tau0, ws.c_smag, ws.g, ws.bc_lo, ws.bc_hi)
     sim.set_wall_velocity(w.u_wall)
-    sim.set_canopy(ws.cd, lad)
+    if w.forest is not None:
+        # the oracle's own codes of the whole point cloud, first nz planes
+        codes, _ = ref.forest_codes(inputs.forest_points(w), w.nx, w.ny, w.nz, w.forest[4])
+        sim.set_forest(ws.cd, w.forest[3], codes[:nz])
+    else:
+        sim.set_canopy(ws.cd, workload_lad(w, ref.lad_lalic, inputs))
     rho, u = inputs.init_fields(ws)
     sim.init(rho, u)
     t0 = time.perf_counter()
@@ -130,18 +149,19 @@ def main():
     ap.add_argument("--variants", default="f64,f16s,bf16s,bf16sr",
                     help="other storage types timed on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mlp", action="store_true",
-                    help="also time the learned closure on the same workload")
+    ap.add_argument("--mlp", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the learned closure on the same workload (default on)")
     ap.add_argument("--mlp-storage", default="bf16sr", choices=list(BYTES_PER_ELT))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c5", "abl1", "abl2", "abl3", "channel"],
+                    choices=["c2", "c3", "c5", "abl1", "abl2", "abl3", "channel", "forest"],
                     help="c2: production canopy 512x128x256 (default); c3/c5: 1024x256x512 "
                          "with the 64x32x32 case's physics; abl1-3: the paper's ABL fine mesh "
                          "350x140x280 with LAD cases 1-3; channel: the paper's Re_tau=180 "
-                         "channel 372x62x124")
+                         "channel 372x62x124; forest: heterogeneous forest from a synthetic "
+                         "point cloud (per-cell forest codes) on 512x128x256")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,7 +187,8 @@ def main():
                           "launches": 3}), flush=True)
         return
     w = {"c2": inputs.C2, "c3": inputs.C3, "c5": inputs.C5, "abl1": inputs.ABL1,
-         "abl2": inputs.ABL2, "abl3": inputs.ABL3, "channel": inputs.CHANNEL}[args.workload]
+         "abl2": inputs.ABL2, "abl3": inputs.ABL3, "channel": inputs.CHANNEL,
+         "forest": inputs.FOREST}[args.workload]
     if args.workload == "c2":
         rho, u = inputs.init_fields(w)
         rho_d = torch.from_numpy(rho).cuda()
@@ -185,15 +206,18 @@ def main():
     total_ms, step_ms, diag = run(args.storage, args.steps, args.warmup)
     mlups = w.n * args.steps / (total_ms * 1e-3) / 1e6
     per_launch_s = step_ms * 1e-3 / args.steps
-    algo_bytes = 2 * 19 * BYTES_PER_ELT[args.storage] * w.n
+    # populations read and written once; a heterogeneous forest adds its
+    # 16-bit table index per cell
+    extra = 2 if w.forest is not None else 0
+    algo_bytes = (2 * 19 * BYTES_PER_ELT[args.storage] + extra) * w.n
     achieved = algo_bytes / per_launch_s / 1e9
-    traffic = measured_traffic(args.storage, w.n)
+    traffic = measured_traffic(args.storage, w)
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:
         k = max(50, args.steps // 4)
         t_ms, s_ms, _ = run(st, k, 20)
-        b = 2 * 19 * BYTES_PER_ELT[st] * w.n
+        b = (2 * 19 * BYTES_PER_ELT[st] + extra) * w.n
         variants[st] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
                         "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -210,7 +234,8 @@ def main():
         sim.close()
         variants[args.mlp_storage + "+mlp"] = {
             "MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
-            "hbm_frac": round(2 * 19 * BYTES_PER_ELT[args.mlp_storage] * w.n / (s_ms * 1e-3 / k)
+            "hbm_frac": round((2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
+                              / (s_ms * 1e-3 / k)
                               / 1e9 / HBM_PEAK_GBS, 4),
             "mlp_fallback": d["mlp_fallback"]}
 
@@ -229,7 +254,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz,
                    "storage": args.storage, "closure": "smagorinsky",
-                   "canopy": ("lalic h=%g LAI=%g" % (w.lad_lalic[0], w.lad_lalic[2])
+                   "canopy": ("forest codes: %d trees/1000 ground cells, h %g-%g, a_fm %g" % (
+                                  round(1000 * w.forest[0]), w.forest[1], w.forest[2], w.forest[3])
+                              if w.forest else
+                              "lalic h=%g LAI=%g" % (w.lad_lalic[0], w.lad_lalic[2])
                               if w.lad_lalic else
                               "lalic h=%g a_fm=%g" % (w.lad_profile[0], w.lad_profile[2])
                               if w.lad_profile else

@@ -81,6 +81,8 @@ typedef struct lbm_params {
     int32_t bc_yhi;      /* lbm_bc at y = ny */
     void *stream;        /* hipStream_t to enqueue on; NULL = the null stream */
     double u_wall[3];    /* velocity of an LBM_BC_EQUILIBRIUM boundary (finite) */
+    int32_t forest_map;  /* != 0: reserve device memory for a heterogeneous forest
+                            (lbm_set_forest): 2 bytes per cell + a 512 KiB table */
 } lbm_params;
 
 typedef struct lbm_diag {
@@ -133,6 +135,36 @@ lbm_status lbm_set_stream(lbm_ctx *ctx, void *stream);
 lbm_status lbm_set_canopy(lbm_ctx *ctx, double cd, const double *lad, int32_t ny,
                           int32_t vector_drag);
 
+/* Heterogeneous forest (Sec. 3, the forest description before Algorithm 2,
+ * and Algorithm 2).  Forest code of a cell (uint32, 0 = not forest):
+ *   bits  0-9   h   height of the cell's forest object in cells (1..1023),
+ *                   the rows spanned by its bounding box;
+ *   bits 10-19  y   row of the cell minus the object's lowest row (< h);
+ *   bits 20-31  q_m height of the LAD maximum, y_m = h * q_m / 4096.
+ * Its LAD is afm * r^n * exp(n (1 - r)) of Eq. (af_theory) at y + 1/2, with
+ * r = (h - y_m)/(h - y - 1/2), n = 6 below y_m and 1/2 above; constant_lad
+ * != 0 gives afm in every forest cell (the constant-LAD case of Table
+ * tab:forest_cases).
+ *
+ * lbm_forest_codes (host only): codes [nz][ny][nx] from a point cloud
+ * points [npoints][3] (x, y, z in cell units, the domain is [0,nx) x [0,ny)
+ * x [0,nz)).  A cell holding at least one point is a forest cell; an object
+ * is a set of forest cells connected through faces, periodic in x and z;
+ * q_m = round(4096 ym_frac).  nobjects (may be NULL) receives the object
+ * count.  EINVAL for a point outside the domain or not finite, ym_frac
+ * outside [0, 4095.5/4096), an object taller than 1023 rows, or NULL codes. */
+lbm_status lbm_forest_codes(const double *points, int64_t npoints, int32_t nx, int32_t ny,
+                            int32_t nz, double ym_frac, uint32_t *codes, int64_t *nobjects);
+
+/* Use per-cell forest codes (host array [nz][ny][nx], copied) instead of the
+ * per-row LAD of lbm_set_canopy, until the next lbm_set_canopy.  The drag is
+ * that of lbm_set_canopy with the cell's LAD.  The library keeps a table of
+ * the distinct codes' LAD (FP64) and a 16-bit table index per cell.  ESTATE if
+ * the context was created without forest_map; EINVAL for NULL codes, a code
+ * with y >= h, more than 65535 distinct codes, or a non-finite cd or afm. */
+lbm_status lbm_set_forest(lbm_ctx *ctx, double cd, double afm, int32_t constant_lad,
+                          const uint32_t *codes, int32_t vector_drag);
+
 /* Eddy-viscosity closure.  LBM_CLOSURE_SMAG (blob ignored) restores Sec. 2.2.
  * LBM_CLOSURE_MLP loads a learned closure blob (host memory, nbytes == 10184,
  * format below) that replaces nu_t of Sec. 2.2 where its 9 input features lie
@@ -148,7 +180,8 @@ lbm_status lbm_set_canopy(lbm_ctx *ctx, double cd, const double *lad, int32_t ny
  * Network: z = (x - mean)/std; h1 = gelu(W1 z + b1); h2 = gelu(W2 h1 + b2);
  * nu_t = s * softplus(w3.h2 + b3), gelu the tanh form.  Features, with
  * P = Pi_neq/(rho/3) and n = e_y: tr P, tr P^2, tr P^3, n.P.n, n.P^2.n,
- * sqrt(tr P^2), y_j/h, lad[j], 1.  Then tau = tau0 + 3 nu_t. */
+ * sqrt(tr P^2), y_j/h, lad[j] (the cell's LAD with lbm_set_forest), 1.  Then
+ * tau = tau0 + 3 nu_t. */
 lbm_status lbm_set_closure(lbm_ctx *ctx, int32_t closure, const void *blob, size_t nbytes);
 
 /* Initial state: f = feq(rho, u) (Sec. 2.1, Eq. local_eq) taken as the

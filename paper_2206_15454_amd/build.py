@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmx.so")
 SOURCES = ["lbm_kernels.hip", "mlp_kernels.hip", "lbm_api.hip", "mlp_train.hip",
-           "closure_data.hip"]
+           "closure_data.hip", "forest.hip"]
 ARCH = os.environ.get("LBMX_ARCH", "gfx950")
 
 

@@ -38,6 +38,9 @@ struct lbm_ctx {
     void *f = nullptr;
     void *mom = nullptr;
     double *lad = nullptr;
+    uint16_t *fidx = nullptr;  // per-cell forest table index (forest_map only)
+    double *ftab = nullptr;    // forest LAD table
+    bool forest = false;       // lbm_set_forest active
     double *imp = nullptr;
     double *stats = nullptr;
     double *red = nullptr;   // diag partials [kRedBlocks*6] + final [16]
@@ -55,6 +58,11 @@ struct lbm_ctx {
     int closure = LBM_CLOSURE_SMAG;
     std::string err;
 };
+
+namespace lbmx {  // forest.hip
+bool forest_table(const uint32_t *codes, long long n, double afm, bool constant,
+                  std::vector<uint16_t> &idx, std::vector<double> &table, std::string *why);
+}
 
 namespace {
 
@@ -134,7 +142,7 @@ long long plane_stride(long long n, size_t elt) {
 }
 
 struct Layout {
-    size_t f, mom, lad, imp, stats, red, prof, mlp, total;
+    size_t f, mom, lad, imp, stats, red, prof, mlp, fidx, ftab, total;
 };
 
 Layout layout(const lbm_params *p) {
@@ -160,6 +168,8 @@ Layout layout(const lbm_params *p) {
     L.red = take((size_t)(kRedBlocks * 6 + 16) * 8);
     L.prof = take((size_t)p->ny * 10 * 8);
     L.mlp = take(kMlpDeviceBytes);
+    L.fidx = take(p->forest_map ? (size_t)n * 2 : 0);
+    L.ftab = take(p->forest_map ? (size_t)kForestTable * 8 : 0);
     L.total = off;
     return L;
 }
@@ -255,6 +265,10 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->red = reinterpret_cast<double *>(b + L.red);
     c->prof = reinterpret_cast<double *>(b + L.prof);
     c->mlp = b + L.mlp;
+    if (p->forest_map) {
+        c->fidx = reinterpret_cast<uint16_t *>(b + L.fidx);
+        c->ftab = reinterpret_cast<double *>(b + L.ftab);
+    }
     if (launch_fill(c->lad, 0.0, (size_t)p->ny, c->stream) != hipSuccess ||
         reset_accumulators(c) != LBM_OK) {
         if (c->owns) (void)hipFree(c->base);
@@ -298,6 +312,31 @@ lbm_status lbm_set_canopy(lbm_ctx *c, double cd, const double *lad, int32_t ny,
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_canopy: sync");
     c->cd = cd;
     c->vector_drag = vector_drag ? 1 : 0;
+    c->forest = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_forest(lbm_ctx *c, double cd, double afm, int32_t constant_lad,
+                          const uint32_t *codes, int32_t vector_drag) {
+    if (!c) return LBM_EINVAL;
+    if (!c->fidx)
+        return fail(c, LBM_ESTATE, "lbm_set_forest: context created without forest_map");
+    if (!codes) return fail(c, LBM_EINVAL, "lbm_set_forest: NULL codes");
+    if (!std::isfinite(cd) || !std::isfinite(afm) || afm < 0.0)
+        return fail(c, LBM_EINVAL, "lbm_set_forest: cd and afm must be finite, afm >= 0");
+    std::vector<uint16_t> idx;
+    std::vector<double> table;
+    std::string why;
+    if (!forest_table(codes, c->n, afm, constant_lad != 0, idx, table, &why))
+        return fail(c, LBM_EINVAL, "lbm_set_forest: " + why);
+    HIPCHK(c, hipMemcpyAsync(c->fidx, idx.data(), idx.size() * 2, hipMemcpyHostToDevice, c->stream),
+           "lbm_set_forest: copy");
+    HIPCHK(c, hipMemcpyAsync(c->ftab, table.data(), table.size() * 8, hipMemcpyHostToDevice,
+                             c->stream), "lbm_set_forest: copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_forest: sync");
+    c->cd = cd;
+    c->vector_drag = vector_drag ? 1 : 0;
+    c->forest = true;
     return LBM_OK;
 }
 
@@ -372,6 +411,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     }
     a.cd = c->cd;
     a.lad = c->lad;
+    a.fidx = c->fidx;
+    a.ftab = c->ftab;
     a.mom = c->mom;
     a.imp = c->imp;
     a.stats = c->stats;
@@ -380,6 +421,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->closure == LBM_CLOSURE_MLP) base_flags |= FLAG_MLP;
+    if (c->forest) base_flags |= FLAG_FOREST;
     for (int64_t s = 0; s < nsteps; ++s) {
         a.parity = c->parity;
         a.seed = (uint32_t)(c->t * 0x9E3779B97F4A7C15ULL >> 32) ^ 0x5bd1e995u;

@@ -42,7 +42,8 @@ enum : int {
     FLAG_VECTOR_DRAG = 4,  // canopy drag on all three components
     FLAG_XCD_REMAP = 8,    // keep consecutive tiles on one XCD
     FLAG_IMPULSE = 16,     // accumulate the body-force impulse
-    FLAG_MLP = 32          // learned closure
+    FLAG_MLP = 32,         // learned closure
+    FLAG_FOREST = 64       // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
 };
 
 // Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
@@ -129,6 +130,9 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // stochastically rounded type is read and written there like BF16S
 constexpr int aux_storage(int st) { return st == ST_BF16SR ? ST_BF16S : st; }
 
+// entries of the per-cell forest LAD table (16-bit index; entry 0 = no forest)
+constexpr int kForestTable = 65536;
+
 // Arguments of one fused step launch (passed by value as kernel arguments).
 struct StepArgs {
     void *f;          // population buffer, q-plane stride qs elements
@@ -146,6 +150,8 @@ struct StepArgs {
     double u_wall[3]; // velocity of a forced-equilibrium boundary (density 1)
     double cd;        // canopy drag coefficient
     const double *lad;  // [ny]
+    const uint16_t *fidx;  // [nz][ny][nx] forest table index per cell (FLAG_FOREST)
+    const double *ftab;    // LAD of each forest table entry; entry 0 is 0
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
     double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators

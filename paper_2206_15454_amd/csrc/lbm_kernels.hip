@@ -102,18 +102,15 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         const C uu = uwx * uwx + uwy * uwy + uwz * uwz;
         return (C)weight(q) * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
     };
-    auto from_eq_wall = [&](int cy) -> bool {  // uniform per block
-        const int js = j - cy;
-        return cy != 0 && (js < 0 || js >= ny) && (js < 0 ? a.bc_lo : a.bc_hi) == BC_EQUILIBRIUM;
-    };
+    // Every direction is loaded first (a direction entering through a
+    // forced-equilibrium boundary reads a valid slot of its own cell, as for
+    // bounce-back) and replaced afterwards, so no decode waits inside a
+    // per-direction branch.
     C v[NQ];
     if (a.parity) {
         static_for<NQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            if (from_eq_wall(CY[q]))
-                v[q] = feq_wall(q);
-            else
-                v[q] = CD::ld(f + q * qs + self);
+            v[q] = CD::ld(f + q * qs + self);
         });
     } else {
         static_for<NQ>([&](auto qc) {
@@ -122,16 +119,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             const int js = j - cy;
             if (cy != 0 && (js < 0 || js >= ny) &&
                 (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
-                const int bc = js < 0 ? a.bc_lo : a.bc_hi;
-                if (bc == BC_EQUILIBRIUM)
-                    v[q] = feq_wall(q);
-                else if (bc == BC_BOUNCEBACK)
+                if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
                     v[q] = CD::ld(f + q * qs + self);  // left this cell towards the wall
                 else  // free slip: left the wall row upstream, moving towards the wall
                     v[q] = CD::ld(f + opp(mir(q)) * qs + cell(-cx, 0, -cz));
             } else {
                 v[q] = CD::ld(f + opp(q) * qs + cell(-cx, -cy, -cz));
             }
+        });
+    }
+    if ((j == 0 && a.bc_lo == BC_EQUILIBRIUM) || (j == ny - 1 && a.bc_hi == BC_EQUILIBRIUM)) {
+        static_for<NQ>([&](auto qc) {  // uniform per block (one row per block)
+            constexpr int q = decltype(qc)::value;
+            const int js = j - CY[q];
+            if (CY[q] != 0 && (js < 0 || js >= ny) &&
+                (js < 0 ? a.bc_lo : a.bc_hi) == BC_EQUILIBRIUM)
+                v[q] = feq_wall(q);
         });
     }
 
@@ -162,8 +165,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     C uy = (jy + C(0.5) * rho * gy) * irho;
     C uz = (jz + C(0.5) * rho * gz) * irho;
     C ax = gx, ay = gy, az = gz;  // total acceleration
-    const C lad = (C)a.lad[j];
-    if (lad > C(0)) {  // uniform per block: the block is one row
+    auto drag = [&](C lad) {
         const C speed = sqrt(ux * ux + uy * uy + uz * uz);
         const C kd = -(C)a.cd * lad * speed;  // drag acceleration per unit velocity
         const C adx = kd * ux;
@@ -176,6 +178,16 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             uz += C(0.5) * adz;
         }
         ux += C(0.5) * adx;
+    };
+    // LAD of the cell for a heterogeneous forest, else of the row; the row
+    // test stays uniform per block (the block is one row)
+    C lad;
+    if (a.flags & FLAG_FOREST) {
+        lad = (C)a.ftab[a.fidx[self]];
+        if (lad > C(0)) drag(lad);
+    } else {
+        lad = (C)a.lad[j];
+        if (lad > C(0)) drag(lad);
     }
     const C Fx = rho * ax, Fy = rho * ay, Fz = rho * az;
 

@@ -49,6 +49,9 @@ class Workload:
     u_wall: Tuple[float, float, float] = (0.0, 0.0, 0.0)  # forced-equilibrium boundary
     lad_profile: Optional[Tuple[float, float, float]] = None  # (h, y_m, a_fm): Eq. af_theory peak
     channel: bool = False  # initial profile mirrored about the mid-plane (two walls)
+    # heterogeneous forest from a synthetic point cloud: (trees per ground
+    # cell, min and max tree height in cells, a_fm, y_m / h, points per cell)
+    forest: Optional[Tuple[float, float, float, float, float, float]] = None
     extra: dict = field(default_factory=dict, compare=False, hash=False)
 
     @property
@@ -117,7 +120,13 @@ CHANNEL = Workload(name="paper-channel-372x62x124", nx=372, ny=62, nz=124, stora
                    bc_hi=BC_BOUNCEBACK, cd=0.0, u_ref=0.03, y_ref=31.0, noise=0.05, seed=6,
                    steps=20000, channel=True)
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL)}
+# A heterogeneous forest (Sec. 3 forest codes, Algorithm 2) on the production
+# grid: about 1640 trees of 8-16 cells, crowns that overlap into patches,
+# a_fm = 0.36 per cell (the peak of the LAI-2 profile above), y_m = 0.7 h.
+FOREST = replace(C2, name="forest-patches-512x128x256-f32", lad_lalic=None,
+                 forest=(1.0 / 80.0, 8.0, 16.0, 0.36, 0.7, 4.0), seed=7)
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL, FOREST)}
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
@@ -127,7 +136,7 @@ def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
 
 def lad_constant(w: Workload) -> Optional[np.ndarray]:
     """Constant-LAD canopy rows (None when the workload uses a profile)."""
-    if w.lad_lalic is not None or w.lad_profile is not None:
+    if w.lad_lalic is not None or w.lad_profile is not None or w.forest is not None:
         return None
     lad = np.zeros(w.ny)
     lad[: min(w.canopy_rows, w.ny)] = w.lad_const
@@ -176,3 +185,40 @@ def random_populations(shape, seed: int, base, scale: float = 0.01):
     base = np.asarray(base, dtype=np.float64).reshape((19,) + (1,) * len(shape))
     xi = rng.uniform(-1.0, 1.0, size=(19,) + tuple(shape))
     return base * (1.0 + scale * xi)
+
+
+def forest_points(w: Workload, seed: Optional[int] = None) -> np.ndarray:
+    """Synthetic forest point cloud [npts][3] (x, y, z in cell units).
+
+    Trees stand at uniform random ground positions (periodic in x and z),
+    trees_per_cell * nx * nz of them, with height H ~ U[h_min, h_max].  Each
+    has a trunk (points along the axis from the ground to 0.3 H) and a crown:
+    an ellipsoid centred at 0.65 H with vertical semi-axis 0.35 H and
+    horizontal radius R ~ U[0.2, 0.35] H, filled with uniformly drawn points
+    at points_per_cell per unit volume (so some crown cells hold none, as in
+    a scanned cloud).  NumPy PCG64 ``default_rng(seed)``."""
+    density, hmin, hmax, _, _, ppc = w.forest
+    rng = np.random.default_rng(w.seed if seed is None else seed)
+    ntrees = max(1, int(round(density * w.nx * w.nz)))
+    cx = rng.random(ntrees) * w.nx
+    cz = rng.random(ntrees) * w.nz
+    H = rng.uniform(hmin, hmax, ntrees)
+    R = rng.uniform(0.2, 0.35, ntrees) * H
+    out = []
+    for t in range(ntrees):
+        m = max(1, int(round(0.3 * H[t] * 2)))  # trunk: 2 points per cell of height
+        out.append(np.stack([np.full(m, cx[t]), rng.random(m) * 0.3 * H[t], np.full(m, cz[t])], 1))
+        a, b = R[t], 0.35 * H[t]
+        m = int(round(ppc * 4.0 / 3.0 * np.pi * a * a * b))
+        d = rng.normal(size=(m, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        d *= rng.random((m, 1)) ** (1.0 / 3.0)
+        out.append(np.stack([cx[t] + a * d[:, 0], 0.65 * H[t] + b * d[:, 1],
+                             cz[t] + a * d[:, 2]], 1))
+    p = np.concatenate(out)
+    p[:, 0] %= w.nx
+    p[:, 2] %= w.nz
+    p[p[:, 0] >= w.nx, 0] = 0.0  # a tiny negative value wraps to exactly nx
+    p[p[:, 2] >= w.nz, 2] = 0.0
+    p[:, 1] = np.clip(p[:, 1], 0.0, np.nextafter(w.ny, 0))
+    return p

@@ -28,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("storage", C.c_int32), ("tau0", C.c_double), ("c_smag", C.c_double),
                 ("g", C.c_double * 3), ("bc_ylo", C.c_int32), ("bc_yhi", C.c_int32),
-                ("stream", C.c_void_p), ("u_wall", C.c_double * 3)]
+                ("stream", C.c_void_p), ("u_wall", C.c_double * 3), ("forest_map", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -53,7 +53,7 @@ EXPORTS = ("lbm_lattice", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lb
            "lbm_set_stream", "lbm_set_canopy", "lbm_set_closure", "lbm_init", "lbm_step",
            "lbm_moments", "lbm_stats", "lbm_set_f", "lbm_get_f", "lbm_lad_lalic",
            "lbm_closure_samples", "lbm_train_create", "lbm_train_step", "lbm_train_get",
-           "lbm_train_destroy", "lbm_train_last_error")
+           "lbm_train_destroy", "lbm_train_last_error", "lbm_forest_codes", "lbm_set_forest")
 
 _lib = None
 
@@ -108,6 +108,11 @@ def lib():
         L.lbm_train_destroy.argtypes = [vp]
         L.lbm_train_last_error.restype = C.c_char_p
         L.lbm_train_last_error.argtypes = [vp]
+        L.lbm_forest_codes.restype = i32
+        L.lbm_forest_codes.argtypes = [dp, i64, i32, i32, i32, C.c_double,
+                                       C.POINTER(C.c_uint32), C.POINTER(i64)]
+        L.lbm_set_forest.restype = i32
+        L.lbm_set_forest.argtypes = [vp, C.c_double, C.c_double, i32, C.POINTER(C.c_uint32), i32]
         _lib = L
     return _lib
 
@@ -129,6 +134,21 @@ def lad_lalic(h, ym, ny, afm=1.0, lai=0.0):
     return out
 
 
+def forest_codes(points, nx, ny, nz, ym_frac=0.7):
+    """Per-cell forest codes [nz][ny][nx] (uint32) and the number of forest
+    objects from a point cloud [npts][3] in cell units (the library's host
+    routine)."""
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    codes = np.zeros((nz, ny, nx), dtype=np.uint32)
+    nobj = C.c_int64(0)
+    st = lib().lbm_forest_codes(p.ctypes.data_as(C.POINTER(C.c_double)), p.shape[0], int(nx),
+                                int(ny), int(nz), float(ym_frac),
+                                codes.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(nobj))
+    if st != 0:
+        raise LBMError(st, "invalid point cloud or y_m fraction")
+    return codes, nobj.value
+
+
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
@@ -137,7 +157,8 @@ class LBM:
     """One simulation context on the current GPU."""
 
     def __init__(self, nx, ny, nz, storage="f32", tau0=0.52, c_smag=0.01, g=(0.0, 0.0, 0.0),
-                 bc_lo="bounceback", bc_hi="freeslip", stream=None, u_wall=(0.0, 0.0, 0.0)):
+                 bc_lo="bounceback", bc_hi="freeslip", stream=None, u_wall=(0.0, 0.0, 0.0),
+                 forest_map=False):
         import torch
 
         self.torch = torch
@@ -148,7 +169,7 @@ class LBM:
         self.p = Params(nx, ny, nz, STORAGE[storage], float(tau0), float(c_smag),
                         (C.c_double * 3)(*map(float, g)), bc_lo, bc_hi,
                         C.c_void_p(self.stream.cuda_stream),
-                        (C.c_double * 3)(*map(float, u_wall)))
+                        (C.c_double * 3)(*map(float, u_wall)), int(bool(forest_map)))
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
         self.storage = storage
@@ -201,6 +222,15 @@ class LBM:
         self._check(lib().lbm_set_canopy(self.h, float(cd),
                                          lad.ctypes.data_as(C.POINTER(C.c_double)), lad.size,
                                          int(bool(vector_drag))), "lbm_set_canopy")
+
+    def set_forest(self, cd, afm, codes, constant=False, vector_drag=False):
+        """Per-cell LAD from forest codes (needs forest_map=True)."""
+        codes = np.ascontiguousarray(codes, dtype=np.uint32)
+        if codes.size != self.n:
+            raise ValueError("codes must have nx*ny*nz entries")
+        self._check(lib().lbm_set_forest(self.h, float(cd), float(afm), int(bool(constant)),
+                                         codes.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                         int(bool(vector_drag))), "lbm_set_forest")
 
     def set_closure(self, blob=None):
         if blob is None:

@@ -88,3 +88,24 @@ def make_gpu(w, storage=None):
                 w.bc_hi, u_wall=w.u_wall)
     g.set_canopy(w.cd, oracle_lad(w))
     return g
+
+
+def make_forest_pair(w, storage=None, seed=None, constant=False, vector_drag=False):
+    """(oracle, GPU) simulations of a heterogeneous-forest workload: each side
+    turns the same seeded point cloud into forest codes with its own routine."""
+    from paper_2206_15454_amd import lbm
+
+    _, _, _, afm, ym_frac, _ = w.forest
+    pts = inputs.forest_points(w)
+    oc, _ = ref.forest_codes(pts, w.nx, w.ny, w.nz, ym_frac)
+    gc, _ = lbm.forest_codes(pts, w.nx, w.ny, w.nz, ym_frac)
+    o = ref.RefLBM(w.nx, w.ny, w.nz, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    o.set_wall_velocity(w.u_wall)
+    g = lbm.LBM(w.nx, w.ny, w.nz, storage or w.storage, w.tau0, w.c_smag, w.g, w.bc_lo,
+                w.bc_hi, u_wall=w.u_wall, forest_map=True)
+    o.set_forest(w.cd, afm, oc, constant, vector_drag)
+    g.set_forest(w.cd, afm, gc, constant, vector_drag)
+    rho, u = inputs.init_fields(w, seed)
+    o.init(rho, u)
+    g.init(rho, u)
+    return o, g, oc

@@ -70,7 +70,7 @@ def test_parameter_validation_without_device(lbm):
         d.update(kw)
         return lbm.Params(d["nx"], d["ny"], d["nz"], d["storage"], d["tau0"], d["c_smag"],
                           (C.c_double * 3)(0, 0, 0), d["bc_ylo"], d["bc_yhi"], None,
-                          (C.c_double * 3)(d.get("uw", 0.0), 0, 0))
+                          (C.c_double * 3)(d.get("uw", 0.0), 0, 0), d.get("forest_map", 0))
 
     assert L.lbm_required_bytes(C.byref(P())) > 19 * 8 * 4 * 4 * 4
     assert L.lbm_required_bytes(C.byref(P(bc_yhi=3, uw=0.1))) > 0  # forced equilibrium
@@ -81,7 +81,41 @@ def test_parameter_validation_without_device(lbm):
         h = C.c_void_p()
         assert L.lbm_create(C.byref(P(**bad)), None, 0, C.byref(h)) == 1
         assert not h.value
+    # a forest map reserves 2 bytes per cell and the table
+    assert (L.lbm_required_bytes(C.byref(P(forest_map=1))) - L.lbm_required_bytes(C.byref(P()))
+            >= 8 * 4 * 4 * 2 + 65536 * 8)
     # storage sizes scale the population buffer
     b = [L.lbm_required_bytes(C.byref(P(nx=512, ny=64, nz=64, storage=s))) for s in range(4)]
     assert b[0] > b[1] > b[2] == b[3]
     assert L.lbm_last_error(None) == b"lbm: NULL context"
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_forest_codes_match_oracle(lbm, seed):
+    """The library's point-cloud -> forest-code routine (host only) against
+    the oracle's, bit for bit, on random clouds with clustered trees."""
+    rng = np.random.default_rng(100 + seed)
+    nx, ny, nz = (int(v) for v in rng.integers(4, 24, size=3))
+    pts = []
+    for _ in range(int(rng.integers(1, 8))):
+        cx, cz = rng.random() * nx, rng.random() * nz
+        top = rng.random() * ny
+        m = int(rng.integers(5, 200))
+        pts.append(np.stack([(cx + rng.normal(0, 1.5, m)) % nx, rng.random(m) * top,
+                             (cz + rng.normal(0, 1.5, m)) % nz], axis=1))
+    pts = np.concatenate(pts)
+    frac = float(rng.random() * 0.99)
+    a, na = lbm.forest_codes(pts, nx, ny, nz, frac)
+    b, nb = ref.forest_codes(pts, nx, ny, nz, frac)
+    np.testing.assert_array_equal(a, b)
+    assert na == nb
+
+
+def test_forest_codes_errors(lbm):
+    for pts, frac in (([[4.0, 0.5, 0.5]], 0.7), ([[0.5, -0.1, 0.5]], 0.7),
+                      ([[0.5, 0.5, float("inf")]], 0.7), ([[0.5, 0.5, 0.5]], 1.0),
+                      ([[0.5, 0.5, 0.5]], -0.1)):
+        with pytest.raises(lbm.LBMError):
+            lbm.forest_codes(np.array(pts), 4, 4, 4, frac)
+    codes, n = lbm.forest_codes(np.zeros((0, 3)), 3, 3, 3)
+    assert n == 0 and not codes.any()

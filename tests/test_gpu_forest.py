@@ -1,0 +1,145 @@
+"""Heterogeneous forest on the GPU (per-cell LAD from forest codes, Sec. 3
+forest description and Algorithm 2) against the oracle, which builds its own
+codes from the same point cloud and evaluates Eq. (af_theory) per cell."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2206_15454_amd import inputs
+from tests.gpu_common import make_forest_pair, normwise, require_gpu, round_storage, ulp
+
+pytestmark = pytest.mark.gpu
+
+W = ref.lattice()[1]
+# trees of 6-14 cells, dense enough that a 64x24x32 grid holds several objects
+FW = inputs.scaled(inputs.FOREST, 64, 24, 32, storage="f64",
+                   forest=(1.0 / 30.0, 6.0, 14.0, 0.36, 0.7, 4.0))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_forest_f64_matches_oracle():
+    o, g, codes = make_forest_pair(FW, seed=4)
+    assert (codes > 0).sum() > 500
+    o.step(100)
+    g.step(100)
+    ro, uo, no, do = o.moments()
+    rg, ug, ng, dg = g.moments()
+    e = {"rho": normwise(rg, ro), "u": normwise(ug, uo), "nut": normwise(ng, no)}
+    print("forest 64x24x32 f64 100 steps", e)
+    assert max(e.values()) <= 1e-12
+    assert dg["imp_x"] == pytest.approx(do["imp_x"], rel=1e-12)
+    assert dg["mass"] == pytest.approx(do["mass"], rel=1e-13)
+    # the forest slows the flow inside the crowns
+    inside = codes > 0
+    assert uo[0][inside].mean() < uo[0][~inside].mean()
+
+
+@pytest.mark.parametrize("constant,vector_drag", [(True, False), (False, True)])
+def test_forest_constant_lad_and_vector_drag(constant, vector_drag):
+    w = inputs.scaled(FW, 37, 20, 9)
+    o, g, _ = make_forest_pair(w, seed=2, constant=constant, vector_drag=vector_drag)
+    o.step(25)
+    g.step(25)
+    _, uo, no, _ = o.moments()
+    _, ug, ng, _ = g.moments()
+    assert normwise(ug, uo) <= 1e-12 and normwise(ng, no) <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s"])
+def test_forest_one_step_at_bench_width(storage):
+    """One step from a stored state on a 512-wide grid (the tile width and
+    launch configuration of the 512x128x256 runs), both AA parities."""
+    w = inputs.scaled(inputs.FOREST, 512, 20, 16, storage=storage,
+                      forest=(1.0 / 40.0, 6.0, 14.0, 0.36, 0.7, 4.0))
+    o, g, _ = make_forest_pair(w)
+    S = inputs.random_populations(w.shape, seed=9, base=W, scale=0.02)
+    S = round_storage(S - W[:, None, None, None], storage) + W[:, None, None, None]
+    o.set_f(S)
+    g.set_f(S)
+    for step in (1, 2):
+        o.step(1)
+        g.step(1)
+        so = o.get_f() - W[:, None, None, None]
+        fg = g.get_f()
+        sg = fg - W[:, None, None, None]
+        scale = np.max(np.abs(so), axis=(1, 2, 3), keepdims=True)
+        worst = float(np.max(np.abs(sg - so) / (ulp(so, storage) + 8 * 2.0 ** -24 * scale)))
+        print(storage, "step", step, "max err/bound", worst)
+        assert worst <= 1.0
+        o.set_f(fg)
+
+
+def test_homogeneous_codes_equal_row_profile_bitwise():
+    """Codes of a forest covering every column up to row h-1 give the same
+    populations, bit for bit, as the per-row LAD of Eq. (af_theory)."""
+    from paper_2206_15454_amd import lbm
+
+    w = inputs.scaled(inputs.C1, 40, 16, 8, storage="f32")
+    h = 7
+    pts = np.array([(i + 0.5, j + 0.5, k + 0.5) for i in range(w.nx) for j in range(h)
+                    for k in range(w.nz)])
+    codes, nobj = lbm.forest_codes(pts, w.nx, w.ny, w.nz, 0.7)
+    assert nobj == 1
+    row = lbm.lad_lalic(h, h * 2867 / 4096.0, w.ny, afm=0.4)
+    rho, u = inputs.init_fields(w, 3)
+    sims = []
+    for forest in (False, True):
+        g = lbm.LBM(w.nx, w.ny, w.nz, "f32", w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                    forest_map=True)
+        if forest:
+            g.set_forest(0.3, 0.4, codes)
+        else:
+            g.set_canopy(0.3, row)
+        g.init(rho, 3 * u)
+        g.step(30)
+        sims.append(g)
+    np.testing.assert_array_equal(sims[0].get_f(), sims[1].get_f())
+    # set_canopy switches the per-cell forest off again
+    sims[1].set_canopy(0.3, row)
+    sims[0].step(5)
+    sims[1].step(5)
+    np.testing.assert_array_equal(sims[0].get_f(), sims[1].get_f())
+
+
+def test_forest_learned_closure_matches_oracle():
+    """The learned closure reads the cell's LAD as its feature."""
+    from tests.test_gpu_closure import WIDE_HI, WIDE_LO, blob_with_range
+
+    w = inputs.scaled(FW, 48, 20, 16)
+    o, g, codes = make_forest_pair(w, seed=6)
+    hi = WIDE_HI.copy()
+    hi[7] = 0.2  # cells with LAD above 0.2 fall back to Smagorinsky
+    blob = blob_with_range(WIDE_LO.copy(), hi, seed=3)
+    o.set_closure(ref.MLP(blob))
+    g.set_closure(blob)
+    o.step(1)
+    g.step(1)
+    _, uo, no, do = o.moments()
+    _, ug, ng, dg = g.moments()
+    lad = np.vectorize(lambda c: ref.forest_lad(c, 0.36))(codes)
+    assert do["mlp_fallback"] == dg["mlp_fallback"] == int((lad > 0.2).sum()) > 0
+    fb = lad > 0.2
+    assert normwise(ng[fb], no[fb]) <= 1e-12
+    assert normwise(ng[~fb], no[~fb]) <= 3e-2
+    assert normwise(ug, uo) <= 1e-6
+
+
+def test_forest_errors():
+    from paper_2206_15454_amd import lbm
+
+    g = lbm.LBM(8, 4, 4, "f32")
+    with pytest.raises(lbm.LBMError) as e:
+        g.set_forest(0.2, 0.3, np.zeros((4, 4, 8), dtype=np.uint32))
+    assert e.value.status == 4  # ESTATE: no forest map reserved
+    g = lbm.LBM(8, 4, 4, "f32", forest_map=True)
+    bad = np.zeros((4, 4, 8), dtype=np.uint32)
+    bad[0, 0, 0] = 3 | (3 << 10)  # y = h
+    with pytest.raises(lbm.LBMError) as e:
+        g.set_forest(0.2, 0.3, bad)
+    assert e.value.status == 1
+    with pytest.raises(lbm.LBMError):
+        g.set_forest(0.2, float("nan"), np.zeros((4, 4, 8), dtype=np.uint32))
