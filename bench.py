@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--mlp", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the learned closure on the same workload (default on)")
     ap.add_argument("--mlp-storage", default="bf16sr", choices=list(BYTES_PER_ELT))
+    ap.add_argument("--mlp-every", default="1,4,8",
+                    help="closure intervals timed with the learned closure (1 = every step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -224,20 +226,26 @@ def main():
     if args.mlp:
         from paper_2206_15454_amd import closure
 
-        sim = make_sim(w, args.mlp_storage, lbm, inputs)
-        sim.init(rho_d, u_d)
         # the network trained on the canopy case at twice the resolution (timing
         # does not depend on the weights; the closure is evaluated in every cell)
-        sim.set_closure(closure.trained_blob())
-        k = max(50, args.steps // 4)
-        t_ms, s_ms, d = time_steps(sim, k, 20, torch)
-        sim.close()
-        variants[args.mlp_storage + "+mlp"] = {
-            "MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
-            "hbm_frac": round((2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
-                              / (s_ms * 1e-3 / k)
-                              / 1e9 / HBM_PEAK_GBS, 4),
-            "mlp_fallback": d["mlp_fallback"]}
+        blob = closure.trained_blob()
+        for every in [int(e) for e in args.mlp_every.split(",") if e]:
+            sim = make_sim(w, args.mlp_storage, lbm, inputs)
+            sim.init(rho_d, u_d)
+            sim.set_closure(blob)
+            sim.set_closure_interval(every)
+            k = max(50, args.steps // 4)
+            t_ms, s_ms, d = time_steps(sim, k, 24, torch)
+            sim.close()
+            # steps that reuse nu_t also read it (4 B/cell FP32, 8 B FP64);
+            # evaluating steps write it when it is reused
+            nb = 8 if args.mlp_storage == "f64" else 4
+            b = (2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
+            b += (nb * w.n if every > 1 else 0)
+            name = args.mlp_storage + "+mlp" + ("" if every == 1 else f"/{every}")
+            variants[name] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+                              "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4),
+                              "closure_every": every, "mlp_fallback": d["mlp_fallback"]}
 
     out = {
         "metric": METRIC,

@@ -92,8 +92,8 @@ typedef struct lbm_diag {
     double max_u;        /* max |u| over cells */
     int64_t t;           /* steps done since lbm_init */
     int64_t nonfinite;   /* cells whose rho, u or nu_t is not finite */
-    int64_t mlp_fallback;/* cells of the last step where the learned closure fell
-                            back to Smagorinsky (0 with the Smagorinsky closure) */
+    int64_t mlp_fallback;/* cells where the learned closure fell back to Smagorinsky
+                            in its last evaluation (0 with the Smagorinsky closure) */
 } lbm_diag;
 
 /* D3Q19 direction table: rest; +x,-x,+y,-y,+z,-z; then the twelve edge
@@ -183,6 +183,16 @@ lbm_status lbm_set_forest(lbm_ctx *ctx, double cd, double afm, int32_t constant_
  * sqrt(tr P^2), y_j/h, lad[j] (the cell's LAD with lbm_set_forest), 1.  Then
  * tau = tau0 + 3 nu_t. */
 lbm_status lbm_set_closure(lbm_ctx *ctx, int32_t closure, const void *blob, size_t nbytes);
+
+/* Evaluate the learned closure only on every `every`-th step (1 <= every <=
+ * 1024; default 1 = every step) and let the steps in between reuse, cell by
+ * cell, the nu_t of the last evaluation (kept in the context's moments
+ * buffer).  A cost saving of this library, not of the paper: the steps in
+ * between run at the speed of the Smagorinsky step.  The first step after
+ * this call, lbm_set_closure, lbm_init or lbm_set_f evaluates.  The
+ * diagnostics' mlp_fallback is the count of the last evaluation.  No effect
+ * with the Smagorinsky closure.  EINVAL for every out of range. */
+lbm_status lbm_set_closure_interval(lbm_ctx *ctx, int32_t every);
 
 /* Initial state: f = feq(rho, u) (Sec. 2.1, Eq. local_eq) taken as the
  * post-collision populations at t = 0; resets t, the impulse and the

@@ -235,7 +235,9 @@ typedef struct {
     int64_t stats_n;
     double *stats; /* [ny][10] sums over samples and x-z */
     const struct mlp_ref *mlp;
-    int64_t mlp_fallback;
+    int64_t mlp_fallback; /* cells that fell back in the last evaluation of the network */
+    int closure_every;    /* evaluate the learned closure every this many steps */
+    int closure_lag;      /* steps since its last evaluation (0: evaluate next step) */
 } ref_ctx;
 
 static size_t cell(const ref_ctx *c, int i, int j, int k) {
@@ -263,6 +265,7 @@ void *ref_create(int nx, int ny, int nz, double tau0, double csmag, double gx, d
     c->nut = (double *)calloc(c->n, sizeof(double));
     c->stats = (double *)calloc(10 * (size_t)ny, sizeof(double));
     c->canopy_h = 1.0;
+    c->closure_every = 1;
     if (!c->lad || !c->fa || !c->fb || !c->rho || !c->u || !c->nut || !c->stats) {
         free(c->lad); free(c->fa); free(c->fb); free(c->rho); free(c->u); free(c->nut);
         free(c->stats); free(c);
@@ -324,6 +327,18 @@ void ref_set_closure(void *h, const void *mlp) {
     ref_ctx *c = (ref_ctx *)h;
     c->mlp = (const struct mlp_ref *)mlp;
     c->canopy_h = mlp ? ref_mlp_canopy_h(mlp) : 1.0;
+    c->closure_lag = 0;
+}
+
+/* Learned closure evaluated on every `every`-th step only, its nu_t reused
+ * by the steps in between (a cost saving of this implementation, not of
+ * the paper); the next step evaluates. */
+int ref_set_closure_interval(void *h, int every) {
+    ref_ctx *c = (ref_ctx *)h;
+    if (every < 1) return 1;
+    c->closure_every = every;
+    c->closure_lag = 0;
+    return 0;
 }
 
 /* R11: f*(x, 0) = feq(rho0, u0); moments before any step are rho0, u0, 0 */
@@ -341,6 +356,7 @@ int ref_init(void *h, const double *rho, const double *u) {
     c->t = 0;
     c->impulse[0] = c->impulse[1] = c->impulse[2] = 0.0;
     c->mlp_fallback = 0;
+    c->closure_lag = 0;
     return 0;
 }
 
@@ -348,6 +364,7 @@ int ref_init(void *h, const double *rho, const double *u) {
 void ref_set_f(void *h, const double *f) {
     ref_ctx *c = (ref_ctx *)h;
     memcpy(c->fa, f, NQ * c->n * sizeof(double));
+    c->closure_lag = 0;
 }
 
 void ref_get_f(const void *h, double *f) {
@@ -392,8 +409,8 @@ void ref_pull(const void *h, double *fin) {
 
 /* One cell of one step in the order of Algorithm 1.  fin: streamed
  * populations; writes post-collision fout, moments, the body force. */
-static void collide_cell(const ref_ctx *c, int jrow, size_t xc, const double *fin, double *fout,
-                         double *rho_o, double *u_o, double *nut_o, double *F_o,
+static void collide_cell(const ref_ctx *c, int jrow, size_t xc, int eval, const double *fin,
+                         double *fout, double *rho_o, double *u_o, double *nut_o, double *F_o,
                          int *fallback) {
     double rho, jm[3], Pi[9];
     ref_moments_of(fin, &rho, jm, Pi);
@@ -430,7 +447,10 @@ static void collide_cell(const ref_ctx *c, int jrow, size_t xc, const double *fi
 
     double nut;
     double tau = ref_smag(c->tau0, c->csmag, rho, Pineq, &nut);
-    if (c->mlp) {
+    if (c->mlp && !eval) {
+        nut = c->nut[xc]; /* the learned nu_t of the last evaluation */
+        tau = c->tau0 + nut / CS2;
+    } else if (c->mlp) {
         double feat[9];
         double yh = (jrow + 0.5) / c->canopy_h;
         ref_mlp_features(c->mlp, c->tau0, rho, Pineq, yh, lad, feat);
@@ -475,6 +495,7 @@ int ref_step(void *h, int64_t nsteps) {
     double *Fsum = (double *)calloc(3 * (size_t)c->nz, sizeof(double));
     for (int64_t s = 0; s < nsteps; ++s) {
         int64_t fb_total = 0;
+        const int eval = c->closure_lag == 0;
 #pragma omp parallel for schedule(static) reduction(+ : fb_total)
         for (int k = 0; k < c->nz; ++k) {
             double Fz[3] = {0, 0, 0};
@@ -484,7 +505,7 @@ int ref_step(void *h, int64_t nsteps) {
                     double fin[NQ], fout[NQ], uo[3], Fo[3], r, nt;
                     for (int q = 0; q < NQ; ++q) fin[q] = pull(c, c->fa, q, i, j, k);
                     size_t x = cell(c, i, j, k);
-                    collide_cell(c, j, x, fin, fout, &r, uo, &nt, Fo, &fb);
+                    collide_cell(c, j, x, eval, fin, fout, &r, uo, &nt, Fo, &fb);
                     for (int q = 0; q < NQ; ++q) c->fb[q * n + x] = fout[q];
                     c->rho[x] = r;
                     for (int a = 0; a < 3; ++a) {
@@ -499,7 +520,8 @@ int ref_step(void *h, int64_t nsteps) {
         /* impulse of the body force, summed in a fixed order */
         for (int k = 0; k < c->nz; ++k)
             for (int a = 0; a < 3; ++a) c->impulse[a] += Fsum[3 * (size_t)k + a];
-        c->mlp_fallback += fb_total;
+        if (c->mlp && eval) c->mlp_fallback = fb_total;
+        if (c->mlp) c->closure_lag = (c->closure_lag + 1) % c->closure_every;
         double *tmp = c->fa;
         c->fa = c->fb;
         c->fb = tmp;

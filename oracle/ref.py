@@ -42,6 +42,7 @@ def lib():
         L.ref_moments.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.ref_stats.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, C.POINTER(C.c_int64)]
         L.ref_set_closure.argtypes = [C.c_void_p, C.c_void_p]
+        L.ref_set_closure_interval.argtypes = [C.c_void_p, C.c_int]
         L.ref_set_wall_velocity.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.ref_lattice.argtypes = [C.POINTER(C.c_int), _dp]
         L.ref_feq.argtypes = [C.c_double, _dp, _dp]
@@ -263,6 +264,10 @@ class RefLBM:
     def set_closure(self, mlp):
         self._mlp = mlp
         lib().ref_set_closure(self.h, mlp.h if mlp is not None else None)
+
+    def set_closure_interval(self, every):
+        if lib().ref_set_closure_interval(self.h, int(every)) != 0:
+            raise ValueError("every must be >= 1")
 
     def init(self, rho, u):
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.shape)

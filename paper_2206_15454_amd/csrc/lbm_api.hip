@@ -56,6 +56,10 @@ struct lbm_ctx {
     double cd = 0.0;
     int vector_drag = 0;
     int closure = LBM_CLOSURE_SMAG;
+    int closure_every = 1;   // learned closure evaluated every this many steps
+    int closure_lag = 0;     // steps since its last evaluation (0: evaluate next)
+    int64_t evals = 0;       // evaluations so far (fallback counter slot = evals & 1)
+    int last_fb_slot = 0;    // slot of the last evaluation
     std::string err;
 };
 
@@ -355,6 +359,18 @@ lbm_status lbm_set_closure(lbm_ctx *c, int32_t closure, const void *blob, size_t
            "lbm_set_closure: copy");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_closure: sync");
     c->closure = LBM_CLOSURE_MLP;
+    c->closure_lag = 0;
+    c->evals = 0;
+    c->last_fb_slot = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_closure_interval(lbm_ctx *c, int32_t every) {
+    if (!c) return LBM_EINVAL;
+    if (every < 1 || every > 1024)
+        return fail(c, LBM_EINVAL, "lbm_set_closure_interval: every must be in [1, 1024]");
+    c->closure_every = every;
+    c->closure_lag = 0;
     return LBM_OK;
 }
 
@@ -383,6 +399,7 @@ lbm_status lbm_init(lbm_ctx *c, const double *rho, const double *u, int32_t on_d
     c->t = 0;
     c->parity = 0;
     c->inited = true;
+    c->closure_lag = 0;  // the next step evaluates the learned closure
     c->unstable = false;
     return LBM_OK;
 }
@@ -420,7 +437,6 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     int base_flags = FLAG_IMPULSE;
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
-    if (c->closure == LBM_CLOSURE_MLP) base_flags |= FLAG_MLP;
     if (c->forest) base_flags |= FLAG_FOREST;
     for (int64_t s = 0; s < nsteps; ++s) {
         a.parity = c->parity;
@@ -429,10 +445,25 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         if (s == nsteps - 1) a.flags |= FLAG_MOMENTS;
         const bool sample = c->stats_every > 0 && (c->t + 1) % c->stats_every == 0;
         if (sample) a.flags |= FLAG_STATS;
-        hipError_t e = (c->closure == LBM_CLOSURE_MLP)
-                           ? launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->stream)
-                           : launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
+        // learned closure: the network runs on evaluating steps (and keeps
+        // its nu_t when later steps reuse it); the steps between read nu_t
+        const bool learned = c->closure == LBM_CLOSURE_MLP;
+        const bool evaluate = learned && c->closure_lag == 0;
+        if (evaluate) {
+            a.flags |= FLAG_MLP;
+            if (c->closure_every > 1) a.flags |= FLAG_NUT_OUT;
+            a.fb_slot = (int)(c->evals & 1);
+        } else if (learned) {
+            a.flags |= FLAG_NUT_IN;
+        }
+        hipError_t e = evaluate ? launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->stream)
+                                : launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "lbm_step: launch");
+        if (evaluate) {
+            c->last_fb_slot = a.fb_slot;
+            c->evals += 1;
+        }
+        if (learned) c->closure_lag = (c->closure_lag + 1) % c->closure_every;
         c->parity ^= 1;
         c->t += 1;
         if (sample) c->stats_n += 1;
@@ -478,7 +509,7 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, double *nut, int32_t 
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_moments: sync");
     int64_t fb = 0;
     if (c->closure == LBM_CLOSURE_MLP) {
-        lbm_status s = mlp_fallback_count(c->mlp, c->parity ^ 1, &fb, c->stream);
+        lbm_status s = mlp_fallback_count(c->mlp, c->last_fb_slot, &fb, c->stream);
         if (s != LBM_OK) return fail(c, s, "lbm_moments: fallback count");
     }
     if (d) {
@@ -544,6 +575,7 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *fin, int32_t on_device) {
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_f: sync");
     c->parity = 0;
     c->inited = true;
+    c->closure_lag = 0;  // the next step evaluates the learned closure
     c->unstable = false;
     return LBM_OK;
 }

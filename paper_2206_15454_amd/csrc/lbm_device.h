@@ -43,7 +43,15 @@ enum : int {
     FLAG_XCD_REMAP = 8,    // keep consecutive tiles on one XCD
     FLAG_IMPULSE = 16,     // accumulate the body-force impulse
     FLAG_MLP = 32,         // learned closure
-    FLAG_FOREST = 64       // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
+    FLAG_FOREST = 64,      // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
+    FLAG_NUT_IN = 128,     // nu_t read from the moments' nu_t plane (learned closure reused)
+    FLAG_NUT_OUT = 256     // nu_t written to that plane on every step of the launch
+};
+
+// Compile-time variants of the step (a bit set; chosen at launch from the flags)
+enum : int {
+    VAR_FOREST = 1,        // FLAG_FOREST
+    VAR_NUT_IN = 2         // FLAG_NUT_IN
 };
 
 // Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
@@ -143,6 +151,7 @@ struct StepArgs {
     int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
     int bc_lo, bc_hi;
     int flags;
+    int fb_slot;      // learned closure: fallback counter slot of this evaluation (0/1)
     uint32_t seed;    // stochastic rounding: hash of (seed, step, cell, direction)
     double tau0;      // molecular relaxation time
     double ksmag;     // 18 sqrt(2) C_smag

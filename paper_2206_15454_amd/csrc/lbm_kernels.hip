@@ -62,7 +62,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int ST, bool LEARNED>
+template <int ST, bool LEARNED, int VAR>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
                                           short *zst, double *sh, double (&imp)[3],
                                           typename Codec<ST>::C *pst, unsigned &fallbacks) {
@@ -179,16 +179,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         }
         ux += C(0.5) * adx;
     };
-    // LAD of the cell for a heterogeneous forest, else of the row; the row
-    // test stays uniform per block (the block is one row)
+    // LAD of the cell for a heterogeneous forest, else of the row (uniform
+    // per block: the block is one row)
     C lad;
-    if (a.flags & FLAG_FOREST) {
+    if constexpr ((VAR & VAR_FOREST) != 0)
         lad = (C)a.ftab[a.fidx[self]];
-        if (lad > C(0)) drag(lad);
-    } else {
+    else
         lad = (C)a.lad[j];
-        if (lad > C(0)) drag(lad);
-    }
+    if (lad > C(0)) drag(lad);
     const C Fx = rho * ax, Fy = rho * ay, Fz = rho * az;
 
     // ---- a5: Smagorinsky: Pi_neq = P - drho/3 I - rho u u -----------------
@@ -206,6 +204,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
     const C X = (C)a.ksmag * Qh * irho;
     C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
+    const long long ncell = (long long)nx * ny * nz;
+    if constexpr ((VAR & VAR_NUT_IN) != 0) {
+        // the learned closure's nu_t of its last evaluation, reused
+        nut = static_cast<const C *>(a.mom)[4 * ncell + self];
+    }
     if constexpr (LEARNED) {
         // learned closure where the features are inside the trained range,
         // Smagorinsky (above) elsewhere
@@ -313,14 +316,16 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     }
 
     // ---- a8: moments of this collision -------------------------------------
-    if ((a.flags & FLAG_MOMENTS) && active) {
+    // (FLAG_NUT_OUT: only nu_t, kept for the steps that reuse it)
+    if ((a.flags & (FLAG_MOMENTS | FLAG_NUT_OUT)) && active) {
         C *m = static_cast<C *>(a.mom);
-        const long long n = (long long)nx * ny * nz;
-        m[self] = rho;
-        m[n + self] = ux;
-        m[2 * n + self] = uy;
-        m[3 * n + self] = uz;
-        m[4 * n + self] = nut;
+        if (a.flags & FLAG_MOMENTS) {
+            m[self] = rho;
+            m[ncell + self] = ux;
+            m[2 * ncell + self] = uy;
+            m[3 * ncell + self] = uz;
+        }
+        m[4 * ncell + self] = nut;
     }
 
     // ---- body-force impulse and plane statistics (FP64 accumulators) ------
@@ -354,20 +359,20 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     }
 }
 
-template <int ST>
+template <int ST, int VAR>
 __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     __shared__ double sh[4 * 10];
     int tile = blockIdx.x;
     if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
     double unused[3] = {0.0, 0.0, 0.0};
     unsigned nofb = 0;
-    step_tile<ST, false>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr, nofb);
+    step_tile<ST, false, VAR>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr, nofb);
 }
 
 // Learned closure: persistent blocks keep the network's weight fragments in
 // registers and walk the tiles (linear index it = block + k * grid; with the
 // grid a multiple of 8, every tile of a block stays on the block's XCD).
-template <int ST>
+template <int ST, int VAR>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 3, ST == ST_F64 ? 2 : 3)))
 void lbm_step_mlp_kernel(const StepArgs a) {
@@ -376,7 +381,8 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     __shared__ typename Codec<ST>::C pst[NQ * 256];  // populations parked during the network
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
-    if (blockIdx.x == 0 && tid == 0) P->fallback[a.parity ^ 1] = 0;  // for the next step
+    // fallback counters alternate between evaluations: clear the other one
+    if (blockIdx.x == 0 && tid == 0) P->fallback[a.fb_slot ^ 1] = 0;
     __shared__ bf16x8 w2s[4 * 2 * 64];
     mlp_stage_w2(P, w2s, tid, 256);
     __syncthreads();
@@ -385,13 +391,13 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        step_tile<ST, true>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
+        step_tile<ST, true, VAR>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
     // cells that fell back: one atomic per wave
     unsigned fsum = fallbacks;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
-    if ((tid & 63) == 0 && fsum) atomicAdd(&P->fallback[a.parity], (unsigned long long)fsum);
+    if ((tid & 63) == 0 && fsum) atomicAdd(&P->fallback[a.fb_slot], (unsigned long long)fsum);
     if (a.flags & FLAG_IMPULSE) {
         __syncthreads();  // sh may still be read by the last tile's statistics
         block_accumulate<3>(imp, a.imp + 3 * (long long)blockIdx.x, sh);  // grid <= ntiles
@@ -627,10 +633,21 @@ __global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
+// compile-time variant from the launch flags
+#define LBMX_VARIANT(flags, CALL)                                      \
+    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
+            ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0)) {                \
+    case 0: { constexpr int V = 0; CALL; } break;                      \
+    case VAR_FOREST: { constexpr int V = VAR_FOREST; CALL; } break;    \
+    case VAR_NUT_IN: { constexpr int V = VAR_NUT_IN; CALL; } break;    \
+    default: { constexpr int V = VAR_FOREST | VAR_NUT_IN; CALL; } break; \
+    }
+
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
     if (bx * bz != 256 || a.ntiles < 1) return hipErrorInvalidValue;
     dim3 block(bx, bz), grid(a.ntiles);
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(lbm_step_kernel<S>, grid, block, 0, s, a));
+    LBMX_DISPATCH(storage, LBMX_VARIANT(a.flags, hipLaunchKernelGGL((lbm_step_kernel<S, V>), grid,
+                                                                    block, 0, s, a)));
     return hipGetLastError();
 }
 
@@ -640,14 +657,20 @@ hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipSt
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
+    if (a.flags & FLAG_NUT_IN) return hipErrorInvalidValue;  // the network computes nu_t
     LBMX_DISPATCH(storage, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S>), 256, 0));
+                               &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S, 0>),
+                               256, 0));
     if (e != hipSuccess) return e;
     int grid = (per_cu > 0 ? per_cu : 1) * ncu;
     grid = grid >= 8 ? grid / 8 * 8 : grid;
     if (grid > a.ntiles) grid = a.ntiles;
-    LBMX_DISPATCH(storage, hipLaunchKernelGGL(lbm_step_mlp_kernel<S>, dim3(grid), dim3(bx, bz), 0,
-                                              s, a));
+    if (a.flags & FLAG_FOREST)
+        LBMX_DISPATCH(storage, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, VAR_FOREST>), dim3(grid),
+                                                  dim3(bx, bz), 0, s, a))
+    else
+        LBMX_DISPATCH(storage, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, 0>), dim3(grid),
+                                                  dim3(bx, bz), 0, s, a))
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ EXPORTS = ("lbm_lattice", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lb
            "lbm_set_stream", "lbm_set_canopy", "lbm_set_closure", "lbm_init", "lbm_step",
            "lbm_moments", "lbm_stats", "lbm_set_f", "lbm_get_f", "lbm_lad_lalic",
            "lbm_closure_samples", "lbm_train_create", "lbm_train_step", "lbm_train_get",
-           "lbm_train_destroy", "lbm_train_last_error", "lbm_forest_codes", "lbm_set_forest")
+           "lbm_train_destroy", "lbm_train_last_error", "lbm_forest_codes", "lbm_set_forest",
+           "lbm_set_closure_interval")
 
 _lib = None
 
@@ -111,6 +112,8 @@ def lib():
         L.lbm_forest_codes.restype = i32
         L.lbm_forest_codes.argtypes = [dp, i64, i32, i32, i32, C.c_double,
                                        C.POINTER(C.c_uint32), C.POINTER(i64)]
+        L.lbm_set_closure_interval.restype = i32
+        L.lbm_set_closure_interval.argtypes = [vp, i32]
         L.lbm_set_forest.restype = i32
         L.lbm_set_forest.argtypes = [vp, C.c_double, C.c_double, i32, C.POINTER(C.c_uint32), i32]
         _lib = L
@@ -238,6 +241,10 @@ class LBM:
         else:
             blob = bytes(blob)
             self._check(lib().lbm_set_closure(self.h, 1, blob, len(blob)), "lbm_set_closure")
+
+    def set_closure_interval(self, every):
+        """Evaluate the learned closure every `every` steps, reuse its nu_t between."""
+        self._check(lib().lbm_set_closure_interval(self.h, int(every)), "lbm_set_closure_interval")
 
     def init(self, rho, u):
         pr, dr, kr = self._in(rho, self.n)

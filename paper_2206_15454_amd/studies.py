@@ -7,6 +7,11 @@
       (512x128x256) with BF16S storage + learned closure against FP32 storage
       + Smagorinsky (and a perturbed FP32 run for the chaotic noise floor),
       profiles averaged in time and over x-z; throughput of both forms.
+  python -m paper_2206_15454_amd.studies interval --out DIR
+      the trained closure evaluated every k = 1, 2, 4, 8 steps (nu_t reused
+      in between) on the production canopy case against FP32 + Smagorinsky.
+  python -m paper_2206_15454_amd.studies abl --out DIR
+      the paper's ABL cases 1-3 (350x140x280): mean profiles, u_* at y/h = 2.
   python -m paper_2206_15454_amd.studies precision --out DIR
       storage precision on 1024x256x512 (physics of the 64x32x32 canopy
       case): FP32 / FP16S / BF16S fields after 1000 steps against the GPU FP64
@@ -75,7 +80,18 @@ def profiles(prof):
     u, v, w = prof[:, 0], prof[:, 1], prof[:, 2]
     var = np.maximum(prof[:, 3:6] - prof[:, 0:3] ** 2, 0.0)
     return {"u": u, "v": v, "w": w, "u_rms": np.sqrt(var[:, 0]), "v_rms": np.sqrt(var[:, 1]),
-            "w_rms": np.sqrt(var[:, 2]), "uv": prof[:, 6] - u * v, "nu_t": prof[:, 9]}
+            "w_rms": np.sqrt(var[:, 2]), "uv": prof[:, 6] - u * v, "vw": prof[:, 8] - v * w,
+            "nu_t": prof[:, 9]}
+
+
+def friction_velocity(prof, y):
+    """u_* = (<u'v'>^2 + <v'w'>^2)^(1/4) at height y (cell centres j + 1/2,
+    linear interpolation between rows), the definition of Sec. 5.1."""
+    p = profiles(prof)
+    yc = np.arange(prof.shape[0]) + 0.5
+    uv = float(np.interp(y, yc, p["uv"]))
+    vw = float(np.interp(y, yc, p["vw"]))
+    return (uv * uv + vw * vw) ** 0.25
 
 
 def coarsen_profile(prof):
@@ -314,13 +330,101 @@ def precision_study(out, steps=1000, long_steps=20000, avg_from=10000,
     return res
 
 
+# ---------------------------------------------------------------------------
+# learned closure evaluated every k steps
+# ---------------------------------------------------------------------------
+
+def interval_study(out, coarse_steps=20000, avg_from=10000, intervals=(1, 2, 4, 8)):
+    """A-posteriori error of the trained closure when it is evaluated only on
+    every k-th step (nu_t reused in between), on the production canopy case,
+    against FP32 + Smagorinsky, with the perturbed-start noise floor."""
+    import torch
+
+    dev = torch.device("cuda")
+    wc = inputs.C2
+    blob = closure.trained_blob()
+    rho, u = inputs.init_fields_torch(wc, dev)
+    runs = {"f32_smag": ("f32", None, 0.0, 1), "f32_smag_perturbed": ("f32", None, 1e-7, 1),
+            "f32_smag_perturbed2": ("f32", None, -1e-7, 1), "f32_mlp": ("f32", blob, 0.0, 1)}
+    for k in intervals:
+        runs[f"bf16sr_mlp_every{k}"] = ("bf16sr", blob, 0.0, k)
+    runs["f16s_mlp_every4"] = ("f16s", blob, 0.0, 4)
+    res = {"workload": wc.name, "steps": coarse_steps, "avg_from": avg_from, "runs": {},
+           "errors": {}, "profiles": {}}
+    profs = {}
+    for name, (st, b, eps, every) in runs.items():
+        sim = make(wc, st, rho, u if eps == 0.0 else u * (1.0 + eps), b)
+        if b is not None:
+            sim.set_closure_interval(every)
+        ms = timed_steps(sim, avg_from, torch, 5000, name)
+        sim.stats_reset()
+        sim.stats_enable(10)
+        ms += timed_steps(sim, coarse_steps - avg_from, torch, 5000, name)
+        prof, ns = sim.stats_read()
+        d = sim.diag()
+        sim.close()
+        profs[name] = prof
+        h = wc.lad_lalic[0]
+        res["runs"][name] = {"MLUPS": wc.n * coarse_steps / ms / 1e3, "closure_every": every,
+                             "stat_samples": ns, "max_u": d["max_u"],
+                             "mlp_fallback_last_eval": d["mlp_fallback"],
+                             "u_star_2h": friction_velocity(prof, 2 * h)}
+        res["profiles"][name] = {k: v.tolist() for k, v in profiles(prof).items()}
+        _log(name, json.dumps(res["runs"][name]))
+    for name in runs:
+        if name != "f32_smag":
+            res["errors"][name] = profile_errors(profs[name], profs["f32_smag"])
+    _log("errors vs f32_smag:", json.dumps({k: round(v["u"], 5) for k, v in res["errors"].items()}))
+    with open(os.path.join(out, "interval_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+# ---------------------------------------------------------------------------
+# the paper's ABL over a homogeneous forest (Sec. 5), fine mesh
+# ---------------------------------------------------------------------------
+
+def abl_study(out, steps=20000, avg_from=10000):
+    """LAD cases 1-3 of Table tab:forest_cases on 350x140x280: mean velocity
+    profile over y/h, u_* at y/h = 2 (Sec. 5.1) and throughput."""
+    import torch
+
+    dev = torch.device("cuda")
+    res = {"steps": steps, "avg_from": avg_from, "cases": {}}
+    for w in (inputs.ABL1, inputs.ABL2, inputs.ABL3):
+        rho, u = inputs.init_fields_torch(w, dev)
+        sim = make(w, w.storage, rho, u)
+        ms = timed_steps(sim, avg_from, torch, 5000, w.name)
+        sim.stats_reset()
+        sim.stats_enable(10)
+        ms += timed_steps(sim, steps - avg_from, torch, 5000, w.name)
+        prof, ns = sim.stats_read()
+        d = sim.diag()
+        sim.close()
+        h = 7.0
+        p = profiles(prof)
+        ustar = friction_velocity(prof, 2 * h)
+        res["cases"][w.name] = {"MLUPS": w.n * steps / ms / 1e3, "stat_samples": ns,
+                                "max_u": d["max_u"], "u_star_2h": ustar,
+                                "y_over_h": ((np.arange(w.ny) + 0.5) / h).tolist(),
+                                "u_over_ustar": (p["u"] / ustar).tolist(),
+                                "u_rms_over_ustar": (p["u_rms"] / ustar).tolist()}
+        _log(w.name, json.dumps({k: res["cases"][w.name][k]
+                                 for k in ("MLUPS", "u_star_2h", "max_u")}))
+    with open(os.path.join(out, "abl_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["closure", "precision"])
+    ap.add_argument("study", choices=["closure", "precision", "interval", "abl"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
     ap.add_argument("--long-steps", type=int, default=20000)
+    ap.add_argument("--avg-from", type=int, default=None,
+                    help="first step of the statistics window (default: half the run)")
     args = ap.parse_args()
     import torch
 
@@ -332,8 +436,13 @@ def main():
         f = args.fine_steps
         closure_study(args.out, fine_steps=f, snapshots=(f // 2, 3 * f // 4, f),
                       coarse_steps=args.coarse_steps, avg_from=args.coarse_steps // 2)
-    else:
+    elif args.study == "precision":
         precision_study(args.out, long_steps=args.long_steps, avg_from=args.long_steps // 2)
+    elif args.study == "interval":
+        interval_study(args.out, coarse_steps=args.coarse_steps,
+                       avg_from=args.avg_from or args.coarse_steps // 2)
+    else:
+        abl_study(args.out, steps=args.long_steps, avg_from=args.avg_from or args.long_steps // 2)
 
 
 if __name__ == "__main__":

@@ -113,3 +113,57 @@ def test_learned_closure_matches_oracle():
     print("after 10 steps: u", normwise(ug, uo), "nu_t", normwise(ng, no))
     assert normwise(ug, uo) <= 1e-5
     assert normwise(ng, no) <= 5e-2
+
+
+def test_closure_interval_matches_oracle():
+    """Learned closure evaluated every 3 steps: the steps in between reuse
+    the nu_t of the last evaluation, on the GPU as in the oracle."""
+    w = inputs.scaled(inputs.C1, 48, 16, 8, canopy_rows=5)
+    o, g = make_pair(w, storage="f64", seed=6)
+    hi = WIDE_HI.copy()
+    hi[7] = 0.15  # canopy rows fall back to Smagorinsky
+    blob = blob_with_range(WIDE_LO.copy(), hi, seed=3)
+    m = ref.MLP(blob)
+    o.set_closure(m)
+    g.set_closure(blob)
+    o.set_closure_interval(3)
+    g.set_closure_interval(3)
+    nut = {}
+    for t in range(1, 8):
+        o.step(1)
+        g.step(1)
+        _, uo, no, do = o.moments()
+        _, ug, ng, dg = g.moments()
+        nut[t] = ng
+        assert do["mlp_fallback"] == dg["mlp_fallback"] == 48 * 5 * 8
+        assert normwise(ng, no) <= 5e-2 and normwise(ug, uo) <= 1e-5, t
+    np.testing.assert_array_equal(nut[2], nut[1])
+    np.testing.assert_array_equal(nut[3], nut[1])
+    np.testing.assert_array_equal(nut[6], nut[4])
+    assert np.max(np.abs(nut[4] - nut[3])) > 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16sr"])
+def test_closure_interval_with_a_constant_network_is_exact(storage):
+    """With a network whose output does not depend on its input, reusing its
+    nu_t changes nothing: populations bit-identical to evaluating every step;
+    interval 1 is the default."""
+    p = random_params(4)
+    p[-65:-1] = 0.0  # w3 = 0: the output is softplus(b3)
+    blob = closure.make_blob(p, MEAN, STD, WIDE_LO, WIDE_HI, 1e-4, 10.0)
+    w = inputs.scaled(inputs.C1, 64, 12, 8)
+    sims = []
+    for every in (None, 1, 5):
+        _, g = make_pair(w, storage=storage, seed=3)
+        g.set_closure(blob)
+        if every is not None:
+            g.set_closure_interval(every)
+        g.step(12)
+        sims.append(g)
+    f0 = sims[0].get_f()
+    np.testing.assert_array_equal(sims[1].get_f(), f0)
+    np.testing.assert_array_equal(sims[2].get_f(), f0)
+    from paper_2206_15454_amd import lbm
+
+    with pytest.raises(lbm.LBMError):
+        sims[2].set_closure_interval(0)

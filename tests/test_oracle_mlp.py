@@ -146,3 +146,79 @@ def test_features_invariants():
     assert x[1] == pytest.approx((Qh / (rho / 3)) ** 2, rel=1e-14)
     assert x[0] == pytest.approx(np.trace(Pineq) / (rho / 3), rel=1e-14, abs=1e-18)
     assert tuple(x[6:]) == (0.3, 0.2, 1.0)
+
+
+def _closure_sim(blob, every=None, seed=4):
+    from paper_2206_15454_amd import inputs
+
+    w = inputs.scaled(inputs.C1, 12, 8, 6, canopy_rows=3)
+    s = ref.RefLBM(w.nx, w.ny, w.nz, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    s.set_canopy(w.cd, inputs.lad_constant(w))
+    m = ref.MLP(blob)
+    s.set_closure(m)
+    s._keep = m
+    if every is not None:
+        s.set_closure_interval(every)
+    rho, u = inputs.init_fields(w, seed)
+    s.init(rho, 5 * u)
+    return s
+
+
+def _random_blob(rng, lo, hi, w3_scale=0.1):
+    W1 = rng.normal(size=(NH1, NIN)) * 0.2; b1 = rng.normal(size=NH1) * 0.1
+    W2 = rng.normal(size=(NH2, NH1)) * 0.1; b2 = rng.normal(size=NH2) * 0.1
+    w3 = rng.normal(size=NH2) * w3_scale
+    mean = np.zeros(NIN, dtype=np.float32)
+    std = np.array([1e-3, 1e-6, 1e-9, 1e-3, 1e-6, 1e-3, 1.0, 0.1, 1.0], dtype=np.float32)
+    return _blob(W1, b1, W2, b2, w3, -1.0, mean, std, lo, hi, 2e-3, 3.0)
+
+
+def test_closure_interval_reuses_the_last_evaluation():
+    """Evaluated every 3 steps: nu_t stays, cell by cell, that of the last
+    evaluation; interval 1 is the plain per-step closure; the first step after
+    set-up, set_f or a new interval always evaluates."""
+    rng = np.random.default_rng(8)
+    # feature 7 (LAD) above 0.1 falls back: the canopy rows use Smagorinsky
+    hi = np.full(NIN, 1e30); hi[7] = 0.1
+    blob = _random_blob(rng, np.full(NIN, -1e30), hi)
+    a, b, c = _closure_sim(blob), _closure_sim(blob, 1), _closure_sim(blob, 3)
+    nut = {}
+    for t in range(1, 7):
+        for s in (a, b, c):
+            s.step(1)
+        ra, ua, na, da = a.moments()
+        rb, ub, nb, db = b.moments()
+        _, uc, nc, dc = c.moments()
+        np.testing.assert_array_equal(ub, ua)
+        np.testing.assert_array_equal(nb, na)
+        nut[t] = nc
+        if t == 1:
+            np.testing.assert_array_equal(nc, na)
+            np.testing.assert_array_equal(uc, ua)
+        # the fallback count is that of the last evaluation (the canopy rows)
+        assert dc["mlp_fallback"] == da["mlp_fallback"] == 12 * 3 * 6
+    np.testing.assert_array_equal(nut[2], nut[1])
+    np.testing.assert_array_equal(nut[3], nut[1])
+    assert np.max(np.abs(nut[4] - nut[3])) > 0  # re-evaluated at step 4
+    np.testing.assert_array_equal(nut[6], nut[4])
+    # set_f: the next step evaluates again
+    c.set_f(c.get_f())
+    c.step(1)
+    assert np.max(np.abs(c.moments()[2] - nut[6])) > 0
+
+
+def test_closure_interval_with_a_constant_network_changes_nothing():
+    """A network whose output does not depend on its input (w3 = 0) gives the
+    same nu_t in every cell at every step, so reusing it is exact."""
+    rng = np.random.default_rng(9)
+    blob = _random_blob(rng, np.full(NIN, -1e30), np.full(NIN, 1e30), w3_scale=0.0)
+    a, c = _closure_sim(blob), _closure_sim(blob, 4)
+    a.step(9)
+    c.step(9)
+    _, ua, na, _ = a.moments()
+    _, uc, nc, _ = c.moments()
+    assert np.ptp(na) == 0 and na.flat[0] > 0
+    np.testing.assert_array_equal(uc, ua)
+    np.testing.assert_array_equal(nc, na)
+    with pytest.raises(ValueError):
+        c.set_closure_interval(0)
