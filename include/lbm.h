@@ -168,7 +168,10 @@ lbm_status lbm_set_forest(lbm_ctx *ctx, double cd, double afm, int32_t constant_
 /* Eddy-viscosity closure.  LBM_CLOSURE_SMAG (blob ignored) restores Sec. 2.2.
  * LBM_CLOSURE_MLP loads a learned closure blob (host memory, nbytes == 10184,
  * format below) that replaces nu_t of Sec. 2.2 where its 9 input features lie
- * inside the stored ranges, and falls back to the Smagorinsky value elsewhere.
+ * inside the stored ranges, and falls back to the Smagorinsky value elsewhere
+ * (and in a cell whose hidden activations leave the FP16 range, |x| > 65504:
+ * the device evaluates layer 1 with BF16 operands, the activations and
+ * layer 2 in FP16, all accumulations in FP32).
  * EINVAL for a bad magic, version, shape or size.
  *
  * Blob (little-endian):

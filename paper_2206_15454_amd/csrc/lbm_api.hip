@@ -31,6 +31,7 @@ struct lbm_ctx {
     // launch geometry
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;
+    bool force_wide = false;  // 64-bit population addresses even for small planes
     // device memory
     void *base = nullptr;
     bool owns = false;
@@ -239,6 +240,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->tpp = c->nbx * c->nbz;
     c->ntiles = c->tpp * p->ny;
     if (const char *e = std::getenv("LBMX_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
+    if (const char *e = std::getenv("LBMX_WIDE")) c->force_wide = std::atoi(e) != 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LBM_EDEVICE;
@@ -425,8 +427,13 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     for (int d = 0; d < 3; ++d) {
         a.g[d] = c->p.g[d];
         a.u_wall[d] = c->p.u_wall[d];
+        a.gf[d] = (float)a.g[d];
+        a.u_wallf[d] = (float)a.u_wall[d];
     }
     a.cd = c->cd;
+    a.tau0f = (float)a.tau0;
+    a.ksmagf = (float)a.ksmag;
+    a.cdf = (float)a.cd;
     a.lad = c->lad;
     a.fidx = c->fidx;
     a.ftab = c->ftab;
@@ -438,6 +445,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
+    // planes of 4 GiB or more cannot be addressed by a buffer resource
+    // (LBMX_WIDE=1 forces the 64-bit path, for tests)
+    if ((unsigned long long)c->qs * c->elt >= (1ULL << 32) || c->force_wide)
+        base_flags |= FLAG_WIDE;
     for (int64_t s = 0; s < nsteps; ++s) {
         a.parity = c->parity;
         a.seed = (uint32_t)(c->t * 0x9E3779B97F4A7C15ULL >> 32) ^ 0x5bd1e995u;

@@ -45,13 +45,15 @@ enum : int {
     FLAG_MLP = 32,         // learned closure
     FLAG_FOREST = 64,      // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
     FLAG_NUT_IN = 128,     // nu_t read from the moments' nu_t plane (learned closure reused)
-    FLAG_NUT_OUT = 256     // nu_t written to that plane on every step of the launch
+    FLAG_NUT_OUT = 256,    // nu_t written to that plane on every step of the launch
+    FLAG_WIDE = 512        // a population plane has 2^32 bytes or more
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
 enum : int {
     VAR_FOREST = 1,        // FLAG_FOREST
-    VAR_NUT_IN = 2         // FLAG_NUT_IN
+    VAR_NUT_IN = 2,        // FLAG_NUT_IN
+    VAR_WIDE = 4           // FLAG_WIDE: population planes of 4 GiB or more (64-bit addresses)
 };
 
 // Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
@@ -86,30 +88,34 @@ template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
     using T = double;
     using C = double;
+    static __device__ __forceinline__ C dec(T t) { return t; }
+    static __device__ __forceinline__ T enc(C v, uint32_t = 0) { return v; }
     static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
     static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, v); }
 };
 template <> struct Codec<ST_F32> {
     using T = float;
     using C = float;
+    static __device__ __forceinline__ C dec(T t) { return t; }
+    static __device__ __forceinline__ T enc(C v, uint32_t = 0) { return v; }
     static __device__ __forceinline__ C ld(const T *p) { return pop_ld(p); }
     static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, v); }
 };
 template <> struct Codec<ST_F16S> {
     using T = _Float16;
     using C = float;
-    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) {
-        pop_st(p, (_Float16)v);  // round to nearest even
-    }
+    static __device__ __forceinline__ C dec(T t) { return (float)t; }
+    static __device__ __forceinline__ T enc(C v, uint32_t = 0) { return (_Float16)v; }  // nearest even
+    static __device__ __forceinline__ C ld(const T *p) { return dec(pop_ld(p)); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, enc(v)); }
 };
 template <> struct Codec<ST_BF16S> {
     using T = __bf16;
     using C = float;
-    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) {
-        pop_st(p, (__bf16)v);  // v_cvt_pk_bf16_f32, nearest even
-    }
+    static __device__ __forceinline__ C dec(T t) { return (float)t; }
+    static __device__ __forceinline__ T enc(C v, uint32_t = 0) { return (__bf16)v; }  // nearest even
+    static __device__ __forceinline__ C ld(const T *p) { return dec(pop_ld(p)); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t = 0) { pop_st(p, enc(v)); }
 };
 // BF16 with stochastic rounding: adding 16 uniform random bits below the kept
 // mantissa and truncating rounds up with probability equal to the dropped
@@ -117,10 +123,64 @@ template <> struct Codec<ST_BF16S> {
 template <> struct Codec<ST_BF16SR> {
     using T = __bf16;
     using C = float;
-    static __device__ __forceinline__ C ld(const T *p) { return (float)pop_ld(p); }
-    static __device__ __forceinline__ void st(T *p, C v, uint32_t r) {
+    static __device__ __forceinline__ C dec(T t) { return (float)t; }
+    static __device__ __forceinline__ T enc(C v, uint32_t r) {
         const uint32_t b = __float_as_uint(v) + (r & 0xFFFFu);
-        pop_st(p, __builtin_bit_cast(__bf16, (unsigned short)(b >> 16)));
+        return __builtin_bit_cast(__bf16, (unsigned short)(b >> 16));
+    }
+    static __device__ __forceinline__ C ld(const T *p) { return dec(pop_ld(p)); }
+    static __device__ __forceinline__ void st(T *p, C v, uint32_t r) { pop_st(p, enc(v, r)); }
+};
+
+// Population access of the step kernel, by direction plane q and cell index.
+// PopBuf: buffer resources, one per plane (base f + q qs, the plane's size),
+// with a 32-bit byte offset per cell: the plane address is scalar work and an
+// access costs one 32-bit multiply-add; an access past the plane reads 0 and
+// a store there is dropped.  Needs plane bytes < 2^32.  PopGlobal: plain
+// 64-bit addresses, for larger planes.
+template <int ST> struct PopBuf {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    const T *f;
+    long long qs;
+    uint32_t bytes;  // plane size in bytes
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int q) const {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(f + q * qs), 0, (int)bytes,
+                                                 0x00020000);
+    }
+    __device__ __forceinline__ C ld(int q, int x) const {
+        const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
+        if constexpr (sizeof(T) == 8)
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(q), off, 0, 0)));
+        else if constexpr (sizeof(T) == 4)
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(q), off, 0, 0)));
+        else
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc(q), off, 0, 0)));
+    }
+    __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
+        const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
+        const T t = CD::enc(v, r);
+        if constexpr (sizeof(T) == 8) {
+            using R = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(q), 0, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, t), rsrc(q), off, 0, 0);
+        } else if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t), rsrc(q), off, 0, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), rsrc(q), off,
+                                                  0, 0);
+        }
+    }
+};
+template <int ST> struct PopGlobal {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    T *f;
+    long long qs;
+    __device__ __forceinline__ C ld(int q, int x) const { return CD::ld(f + q * qs + x); }
+    __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
+        CD::st(f + q * qs + x, v, r);
     }
 };
 
@@ -158,6 +218,8 @@ struct StepArgs {
     double g[3];      // driving acceleration
     double u_wall[3]; // velocity of a forced-equilibrium boundary (density 1)
     double cd;        // canopy drag coefficient
+    // the same scalars in FP32 (the arithmetic type of every storage but F64)
+    float gf[3], u_wallf[3], tau0f, ksmagf, cdf;
     const double *lad;  // [ny]
     const uint16_t *fidx;  // [nz][ny][nx] forest table index per cell (FLAG_FOREST)
     const double *ftab;    // LAD of each forest table entry; entry 0 is 0

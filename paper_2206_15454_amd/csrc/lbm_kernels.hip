@@ -69,7 +69,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
-    T *__restrict__ f = static_cast<T *>(a.f);
+    // population planes: buffer resources, or 64-bit addresses for planes of
+    // 4 GiB and more
+    // (the learned-closure kernel keeps 64-bit addresses: its scalar
+    // registers are taken by the network's fragments)
+    using Pop = std::conditional_t<(VAR & VAR_WIDE) != 0 || LEARNED, PopGlobal<ST>, PopBuf<ST>>;
+    Pop pop;
+    pop.f = static_cast<T *>(a.f);
+    pop.qs = a.qs;
+    if constexpr ((VAR & VAR_WIDE) == 0 && !LEARNED)
+        pop.bytes = (uint32_t)(a.qs * (long long)sizeof(T));
+    // kernel scalars in the arithmetic type (FP32 copies avoid per-thread conversions)
+    constexpr bool F32 = std::is_same_v<C, float>;
+    auto sc = [](double d, float fl) -> C {
+        if constexpr (F32) return fl; else return (C)d;
+    };
 
     const int bx = tile % a.nbx;
     const int rest = tile / a.nbx;
@@ -84,20 +98,25 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
 
     // neighbour coordinates with periodic wrap (y wraps only if periodic;
     // otherwise out-of-range rows go through the wall branches)
-    const int xs[3] = {ic == 0 ? nx - 1 : ic - 1, ic, ic == nx - 1 ? 0 : ic + 1};
-    const int zs[3] = {kc == 0 ? nz - 1 : kc - 1, kc, kc == nz - 1 ? 0 : kc + 1};
-    const int ys[3] = {j == 0 ? ny - 1 : j - 1, j, j == ny - 1 ? 0 : j + 1};
+    // The neighbour's index is the own index plus one offset per axis: x
+    // and z wrap per thread (a select), y is uniform per block, so the 18
+    // neighbours cost additions only.
+    const int plane = nx * ny;
+    const int self = (kc * ny + j) * nx + ic;
+    const int xo[3] = {ic == 0 ? nx - 1 : -1, 0, ic == nx - 1 ? 1 - nx : 1};
+    const int yo[3] = {(j == 0 ? ny - 1 : -1) * nx, 0, (j == ny - 1 ? 1 - ny : 1) * nx};
+    const int zo[3] = {kc == 0 ? (nz - 1) * plane : -plane, 0,
+                       kc == nz - 1 ? (1 - nz) * plane : plane};
     auto cell = [&](int dx, int dy, int dz) -> int {
-        return (zs[dz + 1] * ny + ys[dy + 1]) * nx + xs[dx + 1];
+        return self + xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
     };
-    const int self = cell(0, 0, 0);
-    const long long qs = a.qs;
 
     // ---- a1/a2: stream in (AA slot map with walls), decode ----------------
     // a forced-equilibrium boundary supplies feq(1, u_wall) - w for every
     // population entering through it (both parities)
     auto feq_wall = [&](int q) -> C {
-        const C uwx = (C)a.u_wall[0], uwy = (C)a.u_wall[1], uwz = (C)a.u_wall[2];
+        const C uwx = sc(a.u_wall[0], a.u_wallf[0]), uwy = sc(a.u_wall[1], a.u_wallf[1]),
+                uwz = sc(a.u_wall[2], a.u_wallf[2]);
         const C cu = (C)CX[q] * uwx + (C)CY[q] * uwy + (C)CZ[q] * uwz;
         const C uu = uwx * uwx + uwy * uwy + uwz * uwz;
         return (C)weight(q) * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
@@ -110,7 +129,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     if (a.parity) {
         static_for<NQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            v[q] = CD::ld(f + q * qs + self);
+            v[q] = pop.ld(q, self);
         });
     } else {
         static_for<NQ>([&](auto qc) {
@@ -120,11 +139,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             if (cy != 0 && (js < 0 || js >= ny) &&
                 (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
                 if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                    v[q] = CD::ld(f + q * qs + self);  // left this cell towards the wall
+                    v[q] = pop.ld(q, self);  // left this cell towards the wall
                 else  // free slip: left the wall row upstream, moving towards the wall
-                    v[q] = CD::ld(f + opp(mir(q)) * qs + cell(-cx, 0, -cz));
+                    v[q] = pop.ld(opp(mir(q)), cell(-cx, 0, -cz));
             } else {
-                v[q] = CD::ld(f + opp(q) * qs + cell(-cx, -cy, -cz));
+                v[q] = pop.ld(opp(q), cell(-cx, -cy, -cz));
             }
         });
     }
@@ -160,14 +179,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C irho = C(1) / rho;
 
     // ---- a4: velocity with the driving force, canopy drag, corrected u ----
-    const C gx = (C)a.g[0], gy = (C)a.g[1], gz = (C)a.g[2];
+    const C gx = sc(a.g[0], a.gf[0]), gy = sc(a.g[1], a.gf[1]), gz = sc(a.g[2], a.gf[2]);
     C ux = (jx + C(0.5) * rho * gx) * irho;
     C uy = (jy + C(0.5) * rho * gy) * irho;
     C uz = (jz + C(0.5) * rho * gz) * irho;
     C ax = gx, ay = gy, az = gz;  // total acceleration
     auto drag = [&](C lad) {
         const C speed = sqrt(ux * ux + uy * uy + uz * uz);
-        const C kd = -(C)a.cd * lad * speed;  // drag acceleration per unit velocity
+        const C kd = -sc(a.cd, a.cdf) * lad * speed;  // drag acceleration per unit velocity
         const C adx = kd * ux;
         ax += adx;
         if (a.flags & FLAG_VECTOR_DRAG) {
@@ -199,10 +218,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C nyz = pyz - rho * uy * uz;
     const C Qh = sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
                       C(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
-    const C tau0 = (C)a.tau0;
+    const C tau0 = sc(a.tau0, a.tau0f);
     // tau = (tau0 + sqrt(tau0^2 + X))/2, X = 18 sqrt2 C Q^(1/2)/rho, written
     // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
-    const C X = (C)a.ksmag * Qh * irho;
+    const C X = sc(a.ksmag, a.ksmagf) * Qh * irho;
     C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
     const long long ncell = (long long)nx * ny * nz;
     if constexpr ((VAR & VAR_NUT_IN) != 0) {
@@ -241,8 +260,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             constexpr int q = decltype(qc)::value;
             v[q] = pst[q * 256 + tid];
         });
-        if (in_range) nut = (C)(P->scale * mlp_softplus(o));
-        fallbacks += (!in_range && active) ? 1u : 0u;
+        // a cell whose network activations left the FP16 range (|x| > 65504)
+        // gets a non-finite output: it falls back like an out-of-range cell
+        const float learned = P->scale * mlp_softplus(o);
+        const bool use = in_range && __builtin_isfinite(learned);
+        if (use) nut = (C)learned;
+        fallbacks += (!use && active) ? 1u : 0u;
     }
     const C tau = tau0 + C(3) * nut;
     const C itau = C(1) / tau;
@@ -280,19 +303,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     });
 
     // ---- a7: store in place --------------------------------------------------
-    // random bits for stochastic rounding (unused by the other storage types)
-    // (one hash gives the 16 random bits of two directions: low and high half)
-    const uint32_t rbase = (ST == ST_BF16SR) ? mix32(a.seed ^ mix32((uint32_t)self)) : 0u;
+    // random bits for stochastic rounding (unused by the other storage types):
+    // one hash of (step seed, cell), then one xorshift32 step per pair of
+    // directions, whose low and high 16 bits serve the two directions
+    uint32_t rstate = (ST == ST_BF16SR) ? mix32(a.seed ^ ((uint32_t)self * 0x9E3779B1u)) | 1u : 0u;
+    uint32_t rpair = 0;
     auto rnd = [&](int q) -> uint32_t {
         if (ST != ST_BF16SR) return 0u;
-        const uint32_t h = mix32(rbase + 0x9E3779B9u * (uint32_t)(q / 2 + 1));
-        return (q & 1) ? (h >> 16) : h;
+        if ((q & 1) == 0) {  // q = 0 and every second direction start a new word
+            rstate ^= rstate << 13;
+            rstate ^= rstate >> 17;
+            rstate ^= rstate << 5;
+            rpair = rstate;
+        }
+        return (q & 1) ? rpair : (rpair >> 16);
     };
     if (active) {
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                CD::st(f + opp(q) * qs + self, v[q], rnd(q));
+                pop.st(opp(q), self, v[q], rnd(q));
             });
         } else {
             static_for<NQ>([&](auto qc) {
@@ -305,11 +335,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                     // leaving population in the own cell's opposite slot (a
                     // forced-equilibrium boundary never reads it back)
                     if ((jt < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                        CD::st(f + opp(q) * qs + self, v[q], rnd(q));
+                        pop.st(opp(q), self, v[q], rnd(q));
                     else
-                        CD::st(f + mir(q) * qs + cell(cx, 0, cz), v[q], rnd(q));
+                        pop.st(mir(q), cell(cx, 0, cz), v[q], rnd(q));
                 } else {
-                    CD::st(f + q * qs + cell(cx, cy, cz), v[q], rnd(q));
+                    pop.st(q, cell(cx, cy, cz), v[q], rnd(q));
                 }
             });
         }
@@ -383,7 +413,7 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
     // fallback counters alternate between evaluations: clear the other one
     if (blockIdx.x == 0 && tid == 0) P->fallback[a.fb_slot ^ 1] = 0;
-    __shared__ bf16x8 w2s[4 * 2 * 64];
+    __shared__ half8 w2s[4 * 2 * 64];
     mlp_stage_w2(P, w2s, tid, 256);
     __syncthreads();
     const MlpFrag frag = mlp_load_frag(P, tid & 63, w2s);
@@ -636,11 +666,26 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 // compile-time variant from the launch flags
 #define LBMX_VARIANT(flags, CALL)                                      \
     switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
-            ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0)) {                \
+            ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0) |                 \
+            ((flags) & FLAG_WIDE ? VAR_WIDE : 0)) {                    \
+    case 0: { constexpr int V = 0; CALL; } break;                      \
+    case 1: { constexpr int V = 1; CALL; } break;                      \
+    case 2: { constexpr int V = 2; CALL; } break;                      \
+    case 3: { constexpr int V = 3; CALL; } break;                      \
+    case 4: { constexpr int V = 4; CALL; } break;                      \
+    case 5: { constexpr int V = 5; CALL; } break;                      \
+    case 6: { constexpr int V = 6; CALL; } break;                      \
+    default: { constexpr int V = 7; CALL; } break;                     \
+    }
+
+// the learned-closure kernel's variants (it computes nu_t: never VAR_NUT_IN)
+#define LBMX_VARIANT_MLP(flags, CALL)                                  \
+    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
+            ((flags) & FLAG_WIDE ? VAR_WIDE : 0)) {                    \
     case 0: { constexpr int V = 0; CALL; } break;                      \
     case VAR_FOREST: { constexpr int V = VAR_FOREST; CALL; } break;    \
-    case VAR_NUT_IN: { constexpr int V = VAR_NUT_IN; CALL; } break;    \
-    default: { constexpr int V = VAR_FOREST | VAR_NUT_IN; CALL; } break; \
+    case VAR_WIDE: { constexpr int V = VAR_WIDE; CALL; } break;        \
+    default: { constexpr int V = VAR_FOREST | VAR_WIDE; CALL; } break; \
     }
 
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
@@ -658,19 +703,16 @@ hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipSt
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (a.flags & FLAG_NUT_IN) return hipErrorInvalidValue;  // the network computes nu_t
-    LBMX_DISPATCH(storage, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S, 0>),
-                               256, 0));
+    LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(a.flags, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S, V>),
+                               256, 0)));
     if (e != hipSuccess) return e;
     int grid = (per_cu > 0 ? per_cu : 1) * ncu;
     grid = grid >= 8 ? grid / 8 * 8 : grid;
     if (grid > a.ntiles) grid = a.ntiles;
-    if (a.flags & FLAG_FOREST)
-        LBMX_DISPATCH(storage, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, VAR_FOREST>), dim3(grid),
-                                                  dim3(bx, bz), 0, s, a))
-    else
-        LBMX_DISPATCH(storage, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, 0>), dim3(grid),
-                                                  dim3(bx, bz), 0, s, a))
+    LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(a.flags, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, V>),
+                                                                        dim3(grid), dim3(bx, bz),
+                                                                        0, s, a)));
     return hipGetLastError();
 }
 

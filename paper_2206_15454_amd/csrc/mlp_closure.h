@@ -1,6 +1,7 @@
 // mlp_closure.h -- device side of the learned eddy-viscosity closure
-// (internal).  A 9-64-64-1 network with BF16 operands on the matrix cores
-// and FP32 accumulation, evaluated for the 64 cells of a wavefront at once.
+// (internal).  A 9-64-64-1 network on the matrix cores (layer 1 BF16, layer 2
+// FP16 operands, FP32 accumulation), evaluated for the 64 cells of a
+// wavefront at once; the activations are computed in packed FP16.
 //
 // Formulation: activations are kept transposed (units x cells), so that one
 // 16x16 MFMA output tile (lane l holds rows 4*(l/16)+r, r = 0..3, of column
@@ -9,10 +10,10 @@
 // same way in the weights: no data moves between lanes from layer to layer.
 //   layer 1: mfma 16x16x16 bf16, A = [W1 | b1_hi b1_lo | 0] (16 units x 16 k),
 //            B = [z0..z8, 1, 1, 0..] of 16 cells
-//   layer 2: mfma 16x16x32 bf16 (two k steps), A = W2/2 with permuted k,
-//            C initialised with b2 (the inputs are 2 gelu)
-//   output : o = b3 + (w3/2) . 2gelu(h2) (FP32 FMAs, then a sum over the four
-//            lane quarters of a column)
+//   layer 2: mfma 16x16x32 f16 (two k steps), A = W2/2 (FP16) with permuted
+//            k, C initialised with b2 (the inputs are 2 gelu, FP16)
+//   output : o = b3 + (w3/2) . 2gelu(h2) (FP16 pairs, dot2 into FP32, then a
+//            sum over the four lane quarters of a column)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,6 +22,8 @@
 namespace lbmx {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -32,9 +35,9 @@ struct MlpParams {
     float mean[12], istd[12], lo[12], hi[12];  // raw-feature standardisation and range
     float scale, inv_h, b3, pad0;
     short4v w1f[4][64];      // layer-1 A fragments [unit tile][lane]
-    bf16x8 w2f[4][2][64];    // layer-2 A fragments [unit tile][k step][lane]
+    half8 w2f[4][2][64];     // layer-2 A fragments (FP16) [unit tile][k step][lane]
     floatx4 b2f[4][4];       // layer-2 bias in output layout [unit tile][lane quarter]
-    floatx4 w3f[4][4];       // output weights in output layout [unit tile][lane quarter]
+    half2v w3h[4][4][2];     // output weights (FP16 pairs r = 0,1 and 2,3) [tile][quarter]
     unsigned long long fallback[2];  // cells that fell back, per step parity
 };
 
@@ -49,19 +52,20 @@ __host__ __device__ constexpr int mlp_l2_unit_in(int ks, int h, int t) {
 struct MlpFrag {
     short4v w1[4];
     floatx4 b2[4];
-    floatx4 w3[4];
-    const bf16x8 *w2;  // LDS copy of MlpParams::w2f, [unit tile][k step][lane]
+    half2v w3[4][2];
+    const half8 *w2;  // LDS copy of MlpParams::w2f, [unit tile][k step][lane]
 };
 
 __device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane,
-                                                 const bf16x8 *w2_lds) {
+                                                 const half8 *w2_lds) {
     MlpFrag f;
     const int h = lane >> 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         f.w1[u] = p->w1f[u][lane];
         f.b2[u] = p->b2f[u][h];
-        f.w3[u] = p->w3f[u][h];
+        f.w3[u][0] = p->w3h[u][h][0];
+        f.w3[u][1] = p->w3h[u][h][1];
     }
     f.w2 = w2_lds;
     return f;
@@ -69,9 +73,9 @@ __device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane,
 
 // copy the layer-2 fragments into LDS (all threads of the block; the caller
 // synchronises before use)
-__device__ __forceinline__ void mlp_stage_w2(const MlpParams *p, bf16x8 *w2_lds, int tid,
+__device__ __forceinline__ void mlp_stage_w2(const MlpParams *p, half8 *w2_lds, int tid,
                                              int nthreads) {
-    const bf16x8 *src = &p->w2f[0][0][0];
+    const half8 *src = &p->w2f[0][0][0];
     for (int i = tid; i < 4 * 2 * 64; i += nthreads) w2_lds[i] = src[i];
 }
 
@@ -91,6 +95,27 @@ __device__ __forceinline__ float mlp_gelu2(float x) {
     e = __builtin_fmaf(e, y, 1.860028133e-03f);
     e = (y <= 11.56f) ? e : __builtin_fabsf(x);
     return x + e;
+}
+
+// The same in packed FP16, in a form that stays well conditioned in 11-bit
+// arithmetic: with a = |x|, 2 gelu(x) = x + a - G(a), G(a) = a (1 - tanh(a(a)))
+// decays to 0; G is a degree-6 polynomial in a on a <= 3.4 (minimax-weighted
+// least squares, no constant term, coefficients rounded to FP16 from the top
+// down and the rest refitted) and is held at G(3.4) ~ 2e-3 beyond.  Max
+// |error| of gelu in FP16 arithmetic: 5.0e-3 (at the cut), the size of the
+// BF16 rounding of an activation near 3.4.  Two values per instruction.
+__device__ __forceinline__ half2v mlp_gelu2_h2(half2v x) {
+    const half2v a = __builtin_elementwise_abs(x);
+    const half2v c = {(_Float16)3.4f, (_Float16)3.4f};
+    const half2v t = __builtin_elementwise_min(a, c);
+    auto k = [](float v) { return half2v{(_Float16)v, (_Float16)v}; };
+    half2v g = k(0.004772186279296875f);
+    g = __builtin_elementwise_fma(g, t, k(-0.0460205078125f));
+    g = __builtin_elementwise_fma(g, t, k(0.12420654296875f));
+    g = __builtin_elementwise_fma(g, t, k(0.0909423828125f));
+    g = __builtin_elementwise_fma(g, t, k(-0.87255859375f));
+    g = __builtin_elementwise_fma(g, t, k(1.0166015625f));
+    return (x + a) - g * t;
 }
 
 __device__ __forceinline__ float mlp_softplus(float x) {
@@ -147,23 +172,30 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short 
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const short4v zb = *reinterpret_cast<const short4v *>(lds + (16 * ct + col) * 16 + 4 * h);
-        bf16x8 x2[2];
+        half8 x2[2];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
             floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[u], zb, zero, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) x2[u >> 1][(u & 1) * 4 + r] = (__bf16)mlp_gelu2(d[r]);
+            const half2v g0 = mlp_gelu2_h2(half2v{(_Float16)d[0], (_Float16)d[1]});
+            const half2v g1 = mlp_gelu2_h2(half2v{(_Float16)d[2], (_Float16)d[3]});
+            const int o = (u & 1) * 4;
+            x2[u >> 1][o] = g0[0];
+            x2[u >> 1][o + 1] = g0[1];
+            x2[u >> 1][o + 2] = g1[0];
+            x2[u >> 1][o + 3] = g1[1];
         }
         float part = 0.0f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[(2 * u) * 64 + lane], x2[0],
-                                                                f.b2[u], 0, 0, 0);
-            e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.w2[(2 * u + 1) * 64 + lane], x2[1], e,
-                                                        0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) part += f.w3[u][r] * mlp_gelu2(e[r]);
+            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(f.w2[(2 * u) * 64 + lane], x2[0],
+                                                               f.b2[u], 0, 0, 0);
+            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(f.w2[(2 * u + 1) * 64 + lane], x2[1], e,
+                                                       0, 0, 0);
+            const half2v g0 = mlp_gelu2_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
+            const half2v g1 = mlp_gelu2_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
+            part = __builtin_amdgcn_fdot2(g0, f.w3[u][0], part, false);
+            part = __builtin_amdgcn_fdot2(g1, f.w3[u][1], part, false);
         }
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);

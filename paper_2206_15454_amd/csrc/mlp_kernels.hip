@@ -34,6 +34,24 @@ uint16_t to_bf16_bits(float x) {  // round to nearest even (finite inputs)
     return (uint16_t)(u >> 16);
 }
 
+// IEEE half, round to nearest even (finite inputs; overflow saturates to
+// the largest finite half, which the weights never reach)
+uint16_t to_f16_bits(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u;
+    const uint32_t ax = u & 0x7FFFFFFFu;
+    if (ax >= 0x477FF000u) return (uint16_t)(sign | 0x7BFFu);  // >= 65520: saturate
+    if (ax < 0x38800000u) {                                    // below 2^-14: subnormal
+        float a;
+        std::memcpy(&a, &ax, 4);
+        const float q = std::nearbyint(a * 16777216.0f);       // units of 2^-24
+        return (uint16_t)(sign | (uint32_t)q);
+    }
+    uint32_t m = ax + 0xC8000FFFu + ((ax >> 13) & 1u);  // rebias (-112 << 23), round
+    return (uint16_t)(sign | (m >> 13));
+}
+
 float from_bf16_bits(uint16_t b) {
     uint32_t u = (uint32_t)b << 16;
     float x;
@@ -93,16 +111,18 @@ bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why)
             for (int l = 0; l < 64; ++l)
                 for (int t = 0; t < 8; ++t) {
                     const int uo = 16 * ut + l % 16, ui = mlp_l2_unit_in(ks, l / 16, t);
-                    // halved: the device activations are 2 gelu (exact in bf16)
+                    // halved: the device activations are 2 gelu; FP16 holds every
+                    // halved BF16 weight of magnitude >= 2^-14 exactly
                     const float wv = 0.5f * from_bf16_bits(u16_at(b, w2o + 2 * (uo * kMlpH1 + ui)));
-                    P.w2f[ut][ks][l][t] = __builtin_bit_cast(__bf16, to_bf16_bits(wv));
+                    P.w2f[ut][ks][l][t] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
                 }
     for (int ut = 0; ut < 4; ++ut)
         for (int hq = 0; hq < 4; ++hq)
             for (int r = 0; r < 4; ++r) {
                 const int u = 16 * ut + 4 * hq + r;
                 P.b2f[ut][hq][r] = f32_at(b, 184 + 256 + 4 * u);
-                P.w3f[ut][hq][r] = 0.5f * from_bf16_bits(u16_at(b, w3o + 2 * u));
+                const float wv = 0.5f * from_bf16_bits(u16_at(b, w3o + 2 * u));
+                P.w3h[ut][hq][r / 2][r % 2] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
             }
     std::memcpy(dev, &P, sizeof(P));
     return true;

@@ -177,6 +177,21 @@ def test_tile_width_does_not_change_fp64_results(monkeypatch):
         np.testing.assert_array_equal(r, res[0])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
+def test_buffer_and_64bit_addressing_agree(monkeypatch, storage):
+    """The step addresses populations through buffer resources (planes below
+    4 GiB) or 64-bit pointers (larger planes; forced here with LBMX_WIDE):
+    bit-identical populations, both AA parities, walls and a forest."""
+    w = inputs.scaled(inputs.C1, 70, 9, 6, canopy_rows=4)
+    res = []
+    for wide in ("0", "1"):
+        monkeypatch.setenv("LBMX_WIDE", wide)
+        _, g = make_pair(w, storage=storage, seed=7)
+        g.step(7)
+        res.append(g.get_f())
+    np.testing.assert_array_equal(res[1], res[0])
+
+
 def test_errors_and_state_machine():
     from paper_2206_15454_amd import lbm
 
