@@ -416,9 +416,38 @@ def abl_study(out, steps=20000, avg_from=10000):
     return res
 
 
+# ---------------------------------------------------------------------------
+# the small oracle-size cases on the GPU
+# ---------------------------------------------------------------------------
+
+def small_cases(out, repeats=5):
+    """GPU time of the 64x32x32 canopy case (200 steps) and the 128x64x64 crop
+    (1000 steps) per storage type, median of the repeats: the same runs the
+    oracle timing covers on the host."""
+    import torch
+
+    res = {}
+    for w, steps in ((inputs.C1, 200), (inputs.CROP, 1000)):
+        rho, u = inputs.init_fields(w)
+        for st in ("f64", "f32", "bf16sr"):
+            ms = []
+            for _ in range(repeats):
+                sim = make(w, st, rho, u)
+                sim.step(10)
+                torch.cuda.synchronize()
+                ms.append(timed_steps(sim, steps, torch, steps))
+                sim.close()
+            m = float(np.median(ms))
+            res[f"{w.name}/{st}"] = {"steps": steps, "ms": m, "MLUPS": w.n * steps / m / 1e3}
+            _log(w.name, st, json.dumps(res[f"{w.name}/{st}"]))
+    with open(os.path.join(out, "small_cases.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["closure", "precision", "interval", "abl"])
+    ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
@@ -441,6 +470,8 @@ def main():
     elif args.study == "interval":
         interval_study(args.out, coarse_steps=args.coarse_steps,
                        avg_from=args.avg_from or args.coarse_steps // 2)
+    elif args.study == "small":
+        small_cases(args.out)
     else:
         abl_study(args.out, steps=args.long_steps, avg_from=args.avg_from or args.long_steps // 2)
 
