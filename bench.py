@@ -220,7 +220,8 @@ def main():
         k = max(50, args.steps // 4)
         t_ms, s_ms, _ = run(st, k, 20)
         b = (2 * 19 * BYTES_PER_ELT[st] + extra) * w.n
-        variants[st] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+        v = w.n * k / (t_ms * 1e-3) / 1e6
+        variants[st] = {"MLUPS": round(v, 1), "vs_" + args.storage: round(v / mlups, 3),
                         "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4)}
 
     if args.mlp:
@@ -243,7 +244,8 @@ def main():
             b = (2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
             b += (nb * w.n if every > 1 else 0)
             name = args.mlp_storage + "+mlp" + ("" if every == 1 else f"/{every}")
-            variants[name] = {"MLUPS": round(w.n * k / (t_ms * 1e-3) / 1e6, 1),
+            v = w.n * k / (t_ms * 1e-3) / 1e6
+            variants[name] = {"MLUPS": round(v, 1), "vs_" + args.storage: round(v / mlups, 3),
                               "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4),
                               "closure_every": every, "mlp_fallback": d["mlp_fallback"]}
 
