@@ -82,7 +82,7 @@ typedef struct lbm_params {
     void *stream;        /* hipStream_t to enqueue on; NULL = the null stream */
     double u_wall[3];    /* velocity of an LBM_BC_EQUILIBRIUM boundary (finite) */
     int32_t forest_map;  /* != 0: reserve device memory for a heterogeneous forest
-                            (lbm_set_forest): 2 bytes per cell + a 512 KiB table */
+                            (lbm_set_forest): 2 bytes per cell + a 768 KiB table */
 } lbm_params;
 
 typedef struct lbm_diag {

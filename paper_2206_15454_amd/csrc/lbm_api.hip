@@ -41,6 +41,7 @@ struct lbm_ctx {
     double *lad = nullptr;
     uint16_t *fidx = nullptr;  // per-cell forest table index (forest_map only)
     double *ftab = nullptr;    // forest LAD table
+    float *ftabf = nullptr;    // the same in FP32
     bool forest = false;       // lbm_set_forest active
     double *imp = nullptr;
     double *stats = nullptr;
@@ -147,7 +148,7 @@ long long plane_stride(long long n, size_t elt) {
 }
 
 struct Layout {
-    size_t f, mom, lad, imp, stats, red, prof, mlp, fidx, ftab, total;
+    size_t f, mom, lad, imp, stats, red, prof, mlp, fidx, ftab, ftabf, total;
 };
 
 Layout layout(const lbm_params *p) {
@@ -175,6 +176,7 @@ Layout layout(const lbm_params *p) {
     L.mlp = take(kMlpDeviceBytes);
     L.fidx = take(p->forest_map ? (size_t)n * 2 : 0);
     L.ftab = take(p->forest_map ? (size_t)kForestTable * 8 : 0);
+    L.ftabf = take(p->forest_map ? (size_t)kForestTable * 4 : 0);
     L.total = off;
     return L;
 }
@@ -274,6 +276,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     if (p->forest_map) {
         c->fidx = reinterpret_cast<uint16_t *>(b + L.fidx);
         c->ftab = reinterpret_cast<double *>(b + L.ftab);
+        c->ftabf = reinterpret_cast<float *>(b + L.ftabf);
     }
     if (launch_fill(c->lad, 0.0, (size_t)p->ny, c->stream) != hipSuccess ||
         reset_accumulators(c) != LBM_OK) {
@@ -337,7 +340,10 @@ lbm_status lbm_set_forest(lbm_ctx *c, double cd, double afm, int32_t constant_la
         return fail(c, LBM_EINVAL, "lbm_set_forest: " + why);
     HIPCHK(c, hipMemcpyAsync(c->fidx, idx.data(), idx.size() * 2, hipMemcpyHostToDevice, c->stream),
            "lbm_set_forest: copy");
+    std::vector<float> tablef(table.begin(), table.end());
     HIPCHK(c, hipMemcpyAsync(c->ftab, table.data(), table.size() * 8, hipMemcpyHostToDevice,
+                             c->stream), "lbm_set_forest: copy");
+    HIPCHK(c, hipMemcpyAsync(c->ftabf, tablef.data(), tablef.size() * 4, hipMemcpyHostToDevice,
                              c->stream), "lbm_set_forest: copy");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_forest: sync");
     c->cd = cd;
@@ -437,12 +443,14 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.lad = c->lad;
     a.fidx = c->fidx;
     a.ftab = c->ftab;
+    a.ftabf = c->ftabf;
     a.mom = c->mom;
     a.imp = c->imp;
     a.stats = c->stats;
     a.mlp = c->mlp;
     int base_flags = FLAG_IMPULSE;
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
+    if (c->p.g[1] == 0.0 && c->p.g[2] == 0.0 && !c->vector_drag) base_flags |= FLAG_IMPULSE_X;
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
     // planes of 4 GiB or more cannot be addressed by a buffer resource

@@ -46,7 +46,8 @@ enum : int {
     FLAG_FOREST = 64,      // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
     FLAG_NUT_IN = 128,     // nu_t read from the moments' nu_t plane (learned closure reused)
     FLAG_NUT_OUT = 256,    // nu_t written to that plane on every step of the launch
-    FLAG_WIDE = 512        // a population plane has 2^32 bytes or more
+    FLAG_WIDE = 512,       // a population plane has 2^32 bytes or more
+    FLAG_IMPULSE_X = 1024  // g_y = g_z = 0 and x-only drag: the y, z forces are 0
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
@@ -223,6 +224,7 @@ struct StepArgs {
     const double *lad;  // [ny]
     const uint16_t *fidx;  // [nz][ny][nx] forest table index per cell (FLAG_FOREST)
     const double *ftab;    // LAD of each forest table entry; entry 0 is 0
+    const float *ftabf;    // the same in FP32 (FP32 arithmetic)
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
     double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators

@@ -125,6 +125,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // forced-equilibrium boundary reads a valid slot of its own cell, as for
     // bounce-back) and replaced afterwards, so no decode waits inside a
     // per-direction branch.
+    // heterogeneous forest: the cell's table index is loaded before the
+    // populations, so that the dependent table load overlaps with them
+    // (vmcnt retires loads in order: issued after them, each would wait for
+    // all 19)
+    [[maybe_unused]] uint32_t fidx = 0;
+    if constexpr ((VAR & VAR_FOREST) != 0) fidx = a.fidx[self];
+
     C v[NQ];
     if (a.parity) {
         static_for<NQ>([&](auto qc) {
@@ -155,6 +162,17 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                 (js < 0 ? a.bc_lo : a.bc_hi) == BC_EQUILIBRIUM)
                 v[q] = feq_wall(q);
         });
+    }
+
+    // the cell's LAD (heterogeneous forest): issued right behind the
+    // population loads, it needs only the index, which arrived first
+    [[maybe_unused]] C lad_cell = 0;
+    if constexpr ((VAR & VAR_FOREST) != 0) {
+        if constexpr (F32)
+            lad_cell = a.ftabf[fidx];
+        else
+            lad_cell = (C)a.ftab[fidx];
+        __builtin_amdgcn_sched_barrier(0);  // keep the load here
     }
 
     // ---- a3: moments from the shifted values (no cancellation) ------------
@@ -202,7 +220,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // per block: the block is one row)
     C lad;
     if constexpr ((VAR & VAR_FOREST) != 0)
-        lad = (C)a.ftab[a.fidx[self]];
+        lad = lad_cell;
     else
         lad = (C)a.lad[j];
     if (lad > C(0)) drag(lad);
@@ -369,14 +387,19 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             imp[1] += (double)fv[1];
             imp[2] += (double)fv[2];
         } else {
-            // one FP64 accumulator triple per wavefront (no block barrier)
+            // one FP64 accumulator triple per wavefront (no block barrier);
+            // with FLAG_IMPULSE_X the y and z forces are exactly 0
             const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-            const C s0 = wave_sum(fv[0]), s1 = wave_sum(fv[1]), s2 = wave_sum(fv[2]);
+            const bool yz = !(a.flags & FLAG_IMPULSE_X);
+            const C s0 = wave_sum(fv[0]);
+            const C s1 = yz ? wave_sum(fv[1]) : C(0), s2 = yz ? wave_sum(fv[2]) : C(0);
             if ((tid & 63) == 0) {
                 double *acc = a.imp + 3 * (4 * (long long)tile + (tid >> 6));
                 acc[0] += (double)s0;
-                acc[1] += (double)s1;
-                acc[2] += (double)s2;
+                if (yz) {
+                    acc[1] += (double)s1;
+                    acc[2] += (double)s2;
+                }
             }
         }
     }
