@@ -158,12 +158,13 @@ def main():
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c5", "abl1", "abl2", "abl3", "channel", "forest"],
+                    choices=["c2", "c3", "c5", "abl1", "abl2", "abl3", "channel", "forest", "slab"],
                     help="c2: production canopy 512x128x256 (default); c3/c5: 1024x256x512 "
                          "with the 64x32x32 case's physics; abl1-3: the paper's ABL fine mesh "
                          "350x140x280 with LAD cases 1-3; channel: the paper's Re_tau=180 "
                          "channel 372x62x124; forest: heterogeneous forest from a synthetic "
-                         "point cloud (per-cell forest codes) on 512x128x256")
+                         "point cloud (per-cell forest codes) on 512x128x256; slab: one GPU's "
+                         "128x256x512 share of 1024x256x512 split 8 ways along x")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -190,7 +191,7 @@ def main():
         return
     w = {"c2": inputs.C2, "c3": inputs.C3, "c5": inputs.C5, "abl1": inputs.ABL1,
          "abl2": inputs.ABL2, "abl3": inputs.ABL3, "channel": inputs.CHANNEL,
-         "forest": inputs.FOREST}[args.workload]
+         "forest": inputs.FOREST, "slab": inputs.SLAB}[args.workload]
     if args.workload == "c2":
         rho, u = inputs.init_fields(w)
         rho_d = torch.from_numpy(rho).cuda()

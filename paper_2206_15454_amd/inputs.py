@@ -126,7 +126,13 @@ CHANNEL = Workload(name="paper-channel-372x62x124", nx=372, ny=62, nz=124, stora
 FOREST = replace(C2, name="forest-patches-512x128x256-f32", lad_lalic=None,
                  forest=(1.0 / 80.0, 8.0, 16.0, 0.36, 0.7, 4.0), seed=7)
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL, FOREST)}
+# One GPU's share of the 1024x256x512 case split into 8 slabs along x (the
+# decomposition of a multi-GPU run): 128x256x512 cells, the same N as the
+# production case, with the tile shape that a 128-wide slab gives.
+SLAB = replace(C3, name="canopy-abl-slab-128x256x512", nx=128, ny=256, nz=512, storage="f32")
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL, FOREST,
+                                 SLAB)}
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
