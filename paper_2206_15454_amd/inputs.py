@@ -106,6 +106,14 @@ ABL1 = Workload(name="paper-abl-350x140x280-case1", nx=350, ny=140, nz=280, stor
                 bc_lo=BC_BOUNCEBACK, bc_hi=BC_EQUILIBRIUM, cd=0.15,
                 lad_const=0.215 * _DX_ABL, canopy_rows=7, u_ref=0.08, y_ref=140.0, noise=0.05,
                 seed=5, steps=20000, u_wall=(0.08, 0.0, 0.0))
+# the coarse and medium meshes of the paper's mesh study (Table tab:mesh_cost,
+# constant LAD): dx = 5 m and 4 m, forest 4 and 5 cells high
+ABL_COARSE = replace(ABL1, name="paper-abl-200x80x160-case1", nx=200, ny=80, nz=160,
+                     g=((0.08 / 20) ** 2 / 80, 0.0, 0.0), lad_const=0.215 * 5.0, canopy_rows=4,
+                     y_ref=80.0)
+ABL_MEDIUM = replace(ABL1, name="paper-abl-250x100x200-case1", nx=250, ny=100, nz=200,
+                     g=((0.08 / 20) ** 2 / 100, 0.0, 0.0), lad_const=0.215 * 4.0, canopy_rows=5,
+                     y_ref=100.0)
 ABL2 = replace(ABL1, name="paper-abl-350x140x280-case2",
                lad_profile=(7.0, 0.7 * 7.0, 0.38 * _DX_ABL))
 ABL3 = replace(ABL1, name="paper-abl-350x140x280-case3", lad_const=0.0, canopy_rows=0)
@@ -131,8 +139,8 @@ FOREST = replace(C2, name="forest-patches-512x128x256-f32", lad_lalic=None,
 # production case, with the tile shape that a 128-wide slab gives.
 SLAB = replace(C3, name="canopy-abl-slab-128x256x512", nx=128, ny=256, nz=512, storage="f32")
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, CHANNEL, FOREST,
-                                 SLAB)}
+WORKLOADS = {w.name: w for w in (C1, C2, C3, CROP, C4, C5, ABL1, ABL2, ABL3, ABL_COARSE,
+                                 ABL_MEDIUM, CHANNEL, FOREST, SLAB)}
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
