@@ -114,7 +114,8 @@ bool valid_params(const lbm_params *p, std::string *why) {
 // launch geometry: tiles of BX x 1 x BZ cells (BX*BZ = 256), one row each.
 // BX is the widest of 256/128/64 that pads a row least (idle lanes of a
 // ragged last tile cost bandwidth: 350 cells in 256-wide tiles leave 32% of
-// the lanes idle, in 128-wide tiles 9%).
+// the lanes idle, in 128-wide tiles 9%).  32-wide tiles (LBMX_BX=32 only)
+// pad less but were measured slower: their short rows split cache lines.
 void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
     int BX = 256;
     long long best = -1;
@@ -127,7 +128,7 @@ void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
     }
     if (const char *e = std::getenv("LBMX_BX")) {
         int v = std::atoi(e);
-        if (v == 64 || v == 128 || v == 256) BX = v;
+        if (v == 32 || v == 64 || v == 128 || v == 256) BX = v;
     }
     *bx = BX;
     *bz = 256 / BX;

@@ -166,7 +166,7 @@ def test_checkpoint_roundtrip_is_bit_identical():
 def test_tile_width_does_not_change_fp64_results(monkeypatch):
     w = inputs.scaled(inputs.C1, 300, 6, 5)
     res = []
-    for bx in ("64", "128", "256"):
+    for bx in ("32", "64", "128", "256"):
         monkeypatch.setenv("LBMX_BX", bx)
         for remap in ("0", "1"):
             monkeypatch.setenv("LBMX_XCD_REMAP", remap)
