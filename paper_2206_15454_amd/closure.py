@@ -83,6 +83,20 @@ def read_blob(blob):
     return p, mean, std, lo, hi, scale, h
 
 
+def with_range(blob, feature, lo=None, hi=None):
+    """The same closure with the valid range of one raw feature (index or
+    name in FEATURES) changed; cells outside it use Smagorinsky.  The
+    weights are carried over bit for bit."""
+    k = FEATURES.index(feature) if isinstance(feature, str) else int(feature)
+    p, mean, std, rlo, rhi, scale, h = read_blob(blob)
+    rlo, rhi = rlo.copy(), rhi.copy()
+    if lo is not None:
+        rlo[k] = lo
+    if hi is not None:
+        rhi[k] = hi
+    return make_blob(p, mean, std, rlo, rhi, scale, h)
+
+
 def timing_blob(canopy_h, seed=0):
     """A random network whose input ranges admit every cell (for timing the
     closure kernel; its nu_t is small and positive)."""
@@ -104,3 +118,11 @@ def trained_blob():
                         "closure_canopy_512x128x256.bin")
     with open(path, "rb") as f:
         return f.read()
+
+
+def canopy_layer_blob(cut=4.0):
+    """The trained closure used only in the canopy layer, y/h <= cut
+    (Smagorinsky above, through the y/h feature range).  Measured on the
+    production canopy case, it keeps the spanwise fluctuations that the
+    unrestricted closure damps in the upper layer."""
+    return with_range(trained_blob(), "y_over_h", hi=cut)

@@ -10,6 +10,9 @@
   python -m paper_2206_15454_amd.studies interval --out DIR
       the trained closure evaluated every k = 1, 2, 4, 8 steps (nu_t reused
       in between) on the production canopy case against FP32 + Smagorinsky.
+  python -m paper_2206_15454_amd.studies layer --out DIR
+      the trained closure restricted to the canopy layer (y/h <= 4, through
+      its feature range; Smagorinsky above) against the unrestricted one.
   python -m paper_2206_15454_amd.studies abl --out DIR
       the paper's ABL cases 1-3 (350x140x280): mean profiles, u_* at y/h = 2.
   python -m paper_2206_15454_amd.studies precision --out DIR
@@ -380,6 +383,52 @@ def interval_study(out, coarse_steps=20000, avg_from=10000, intervals=(1, 2, 4, 
     return res
 
 
+def layer_study(out, cut=4.0, coarse_steps=20000, avg_from=10000):
+    """The trained closure restricted to the canopy layer (y/h <= cut through
+    its feature range; Smagorinsky above) against the unrestricted closure
+    and FP32 + Smagorinsky on the production canopy case: mean and RMS
+    profile errors, with the perturbed-start noise floor."""
+    import torch
+
+    dev = torch.device("cuda")
+    wc = inputs.C2
+    full = closure.trained_blob()
+    low = closure.with_range(full, "y_over_h", hi=cut)
+    rho, u = inputs.init_fields_torch(wc, dev)
+    runs = {"f32_smag": ("f32", None, 0.0, 1), "f32_smag_perturbed": ("f32", None, 1e-7, 1),
+            "bf16sr_mlp_every1": ("bf16sr", full, 0.0, 1),
+            f"bf16sr_mlp_below{cut:g}h_every1": ("bf16sr", low, 0.0, 1),
+            f"bf16sr_mlp_below{cut:g}h_every8": ("bf16sr", low, 0.0, 8),
+            f"f32_mlp_below{cut:g}h_every1": ("f32", low, 0.0, 1)}
+    res = {"workload": wc.name, "cut_y_over_h": cut, "steps": coarse_steps,
+           "avg_from": avg_from, "runs": {}, "errors": {}, "profiles": {}}
+    profs = {}
+    for name, (st, b, eps, every) in runs.items():
+        sim = make(wc, st, rho, u if eps == 0.0 else u * (1.0 + eps), b)
+        if b is not None:
+            sim.set_closure_interval(every)
+        ms = timed_steps(sim, avg_from, torch, 5000, name)
+        sim.stats_reset()
+        sim.stats_enable(10)
+        ms += timed_steps(sim, coarse_steps - avg_from, torch, 5000, name)
+        prof, ns = sim.stats_read()
+        d = sim.diag()
+        sim.close()
+        profs[name] = prof
+        res["runs"][name] = {"MLUPS": wc.n * coarse_steps / ms / 1e3, "closure_every": every,
+                             "fallback_fraction_last_eval": d["mlp_fallback"] / wc.n}
+        res["profiles"][name] = {k: v.tolist() for k, v in profiles(prof).items()}
+        _log(name, json.dumps(res["runs"][name]))
+    for name in runs:
+        if name != "f32_smag":
+            res["errors"][name] = profile_errors(profs[name], profs["f32_smag"])
+            _log("error vs f32_smag", name, json.dumps({k: round(v, 4)
+                                                        for k, v in res["errors"][name].items()}))
+    with open(os.path.join(out, "layer_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 # ---------------------------------------------------------------------------
 # the paper's ABL over a homogeneous forest (Sec. 5), fine mesh
 # ---------------------------------------------------------------------------
@@ -447,7 +496,7 @@ def small_cases(out, repeats=5):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small"])
+    ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small", "layer"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
@@ -472,6 +521,9 @@ def main():
                        avg_from=args.avg_from or args.coarse_steps // 2)
     elif args.study == "small":
         small_cases(args.out)
+    elif args.study == "layer":
+        layer_study(args.out, coarse_steps=args.coarse_steps,
+                    avg_from=args.avg_from or args.coarse_steps // 2)
     else:
         abl_study(args.out, steps=args.long_steps, avg_from=args.avg_from or args.long_steps // 2)
 

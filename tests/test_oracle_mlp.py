@@ -222,3 +222,28 @@ def test_closure_interval_with_a_constant_network_changes_nothing():
     np.testing.assert_array_equal(nc, na)
     with pytest.raises(ValueError):
         c.set_closure_interval(0)
+
+
+def test_closure_with_range_keeps_the_network():
+    """closure.with_range changes one feature's range and nothing else; the
+    oracle then falls back exactly where that feature leaves it."""
+    from paper_2206_15454_amd import closure
+
+    rng = np.random.default_rng(11)
+    blob = _random_blob(rng, np.full(NIN, -1e30), np.full(NIN, 1e30))
+    low = closure.with_range(blob, "y_over_h", hi=4.0)
+    assert len(low) == len(blob)
+    p0, m0, s0, lo0, hi0, sc0, h0 = closure.read_blob(blob)
+    p1, m1, s1, lo1, hi1, sc1, h1 = closure.read_blob(low)
+    np.testing.assert_array_equal(p0, p1)
+    np.testing.assert_array_equal(lo0, lo1)
+    assert hi1[6] == 4.0 and np.all(np.delete(hi1, 6) == np.delete(hi0, 6))
+    X = rng.normal(size=(40, NIN)) * 1e-3
+    X[:, 6] = np.linspace(0.1, 8.0, 40)
+    smag = np.full(40, 7e-5)
+    n0, f0 = ref.MLP(blob).predict(X, smag)
+    n1, f1 = ref.MLP(low).predict(X, smag)
+    above = X[:, 6] > 4.0
+    assert np.all(f1 == above) and not f0.any()
+    np.testing.assert_array_equal(n1[~above], n0[~above])
+    np.testing.assert_array_equal(n1[above], smag[above])
