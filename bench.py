@@ -159,6 +159,9 @@ def main():
     ap.add_argument("--mlp-storage", default="bf16sr", choices=list(BYTES_PER_ELT))
     ap.add_argument("--mlp-every", default="1,4,8",
                     help="closure intervals timed with the learned closure (1 = every step)")
+    ap.add_argument("--mlp-canopy-every", default="1,8",
+                    help="intervals timed with the closure restricted to the canopy layer "
+                         "(y/h <= 4, Smagorinsky above)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -236,10 +239,13 @@ def main():
     if args.mlp:
         from paper_2206_15454_amd import closure
 
-        # the network trained on the canopy case at twice the resolution (timing
-        # does not depend on the weights; the closure is evaluated in every cell)
-        blob = closure.trained_blob()
-        for every in [int(e) for e in args.mlp_every.split(",") if e]:
+        # the network trained on the canopy case at twice the resolution, used
+        # everywhere and restricted to the canopy layer (a wavefront whose cells
+        # all fall back skips the network, so the restriction is faster)
+        runs = [(closure.trained_blob(), int(e), "") for e in args.mlp_every.split(",") if e]
+        runs += [(closure.canopy_layer_blob(), int(e), "(y<4h)")
+                 for e in args.mlp_canopy_every.split(",") if e]
+        for blob, every, tag in runs:
             sim = make_sim(w, args.mlp_storage, lbm, inputs)
             sim.init(rho_d, u_d)
             sim.set_closure(blob)
@@ -252,7 +258,7 @@ def main():
             nb = 8 if args.mlp_storage == "f64" else 4
             b = (2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
             b += (nb * w.n if every > 1 else 0)
-            name = args.mlp_storage + "+mlp" + ("" if every == 1 else f"/{every}")
+            name = args.mlp_storage + "+mlp" + tag + ("" if every == 1 else f"/{every}")
             v = w.n * k / (t_ms * 1e-3) / 1e6
             variants[name] = {"MLUPS": round(v, 1), "vs_" + args.storage: round(v / mlups, 3),
                               "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4),

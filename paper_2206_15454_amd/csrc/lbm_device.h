@@ -85,6 +85,23 @@ template <class T> __device__ __forceinline__ void pop_st(T *p, T v) {
 // Storage codecs: T is the element type in HBM, C the arithmetic type.
 // Stored values are shifted populations f_q - w_q.  st() takes 32 random bits
 // (used only by the stochastically rounded type).
+// Reciprocal and square root in the arithmetic type of a step.  FP32 uses
+// the hardware instructions (v_rcp_f32, v_sqrt_f32: within 1 ulp of the
+// correctly rounded result, one instruction each instead of a refinement
+// sequence); FP64 keeps the correctly rounded operations.
+template <class C> __device__ __forceinline__ C arith_rcp(C x) {
+    if constexpr (std::is_same_v<C, float>)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return C(1) / x;
+}
+template <class C> __device__ __forceinline__ C arith_sqrt(C x) {
+    if constexpr (std::is_same_v<C, float>)
+        return __builtin_amdgcn_sqrtf(x);
+    else
+        return sqrt(x);
+}
+
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
     using T = double;

@@ -66,6 +66,11 @@ template <int ST, bool LEARNED, int VAR>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
                                           short *zst, double *sh, double (&imp)[3],
                                           typename Codec<ST>::C *pst, unsigned &fallbacks) {
+    // a * b + c is fused only inside one expression, as written: the
+    // rounding then does not depend on how the compiler lays out a kernel's
+    // blocks (the plain and the persistent learned-closure kernels share this
+    // code and give bit-identical populations when every cell falls back)
+#pragma clang fp contract(on)
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
@@ -176,25 +181,30 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     }
 
     // ---- a3: moments from the shifted values (no cancellation) ------------
-    // drho = sum f~, j = sum f~ c, P = sum f~ c c  (f = f~ + w; sum w c c = I/3)
-    C drho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-    static_for<NQ>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
+    // drho = sum f~, j = sum f~ c, P = sum f~ c c  (f = f~ + w; sum w c c = I/3).
+    // Opposite directions q, q+1 enter through their sum (the even moments)
+    // and their difference (the odd moments).  The sums start from -0, which
+    // adds nothing in IEEE arithmetic, so the first term costs no operation.
+    C drho = v[0];
+    C jx = C(-0.0), jy = C(-0.0), jz = C(-0.0);
+    C pxx = C(-0.0), pyy = C(-0.0), pzz = C(-0.0), pxy = C(-0.0), pxz = C(-0.0), pyz = C(-0.0);
+    static_for<(NQ - 1) / 2>([&](auto pc) {
+        constexpr int q = 2 * decltype(pc)::value + 1;  // q and q + 1 = opp(q)
         constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
-        const C x = v[q];
-        drho += x;
-        if (cx) jx += cx > 0 ? x : -x;
-        if (cy) jy += cy > 0 ? x : -x;
-        if (cz) jz += cz > 0 ? x : -x;
-        if (cx) pxx += x;
-        if (cy) pyy += x;
-        if (cz) pzz += x;
-        if (cx && cy) pxy += (cx * cy > 0) ? x : -x;
-        if (cx && cz) pxz += (cx * cz > 0) ? x : -x;
-        if (cy && cz) pyz += (cy * cz > 0) ? x : -x;
+        const C sum = v[q] + v[q + 1], dif = v[q] - v[q + 1];
+        drho += sum;
+        if (cx) jx += cx > 0 ? dif : -dif;
+        if (cy) jy += cy > 0 ? dif : -dif;
+        if (cz) jz += cz > 0 ? dif : -dif;
+        if (cx) pxx += sum;
+        if (cy) pyy += sum;
+        if (cz) pzz += sum;
+        if (cx && cy) pxy += (cx * cy > 0) ? sum : -sum;
+        if (cx && cz) pxz += (cx * cz > 0) ? sum : -sum;
+        if (cy && cz) pyz += (cy * cz > 0) ? sum : -sum;
     });
     const C rho = C(1) + drho;
-    const C irho = C(1) / rho;
+    const C irho = arith_rcp(rho);
 
     // ---- a4: velocity with the driving force, canopy drag, corrected u ----
     const C gx = sc(a.g[0], a.gf[0]), gy = sc(a.g[1], a.gf[1]), gz = sc(a.g[2], a.gf[2]);
@@ -203,7 +213,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     C uz = (jz + C(0.5) * rho * gz) * irho;
     C ax = gx, ay = gy, az = gz;  // total acceleration
     auto drag = [&](C lad) {
-        const C speed = sqrt(ux * ux + uy * uy + uz * uz);
+        const C speed = arith_sqrt(ux * ux + uy * uy + uz * uz);
         const C kd = -sc(a.cd, a.cdf) * lad * speed;  // drag acceleration per unit velocity
         const C adx = kd * ux;
         ax += adx;
@@ -234,13 +244,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C nxy = pxy - rho * ux * uy;
     const C nxz = pxz - rho * ux * uz;
     const C nyz = pyz - rho * uy * uz;
-    const C Qh = sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
+    const C Qh = arith_sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
                       C(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
     const C tau0 = sc(a.tau0, a.tau0f);
     // tau = (tau0 + sqrt(tau0^2 + X))/2, X = 18 sqrt2 C Q^(1/2)/rho, written
     // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
     const C X = sc(a.ksmag, a.ksmagf) * Qh * irho;
-    C nut = X / (C(6) * (sqrt(tau0 * tau0 + X) + tau0));
+    C nut = X * arith_rcp(C(6) * (arith_sqrt(tau0 * tau0 + X) + tau0));
     const long long ncell = (long long)nx * ny * nz;
     if constexpr ((VAR & VAR_NUT_IN) != 0) {
         // the learned closure's nu_t of its last evaluation, reused
@@ -265,57 +275,69 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         z[9] = z[10] = bf16_bits(1.0f);
 #pragma unroll
         for (int c = 11; c < 16; ++c) z[c] = 0;
-        // park the populations in LDS while the network runs (frees registers)
-        static_for<NQ>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            pst[q * 256 + tid] = v[q];
-        });
-        wave_lds_sync();  // the previous tile's reads of this wave's staging area are done
-        mlp_stage_inputs(zst, lane, z);
-        wave_lds_sync();
-        const float o = mlp_forward_wave(frag, zst, lane) + P->b3;
-        static_for<NQ>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            v[q] = pst[q * 256 + tid];
-        });
-        // a cell whose network activations left the FP16 range (|x| > 65504)
-        // gets a non-finite output: it falls back like an out-of-range cell
-        const float learned = P->scale * mlp_softplus(o);
-        const bool use = in_range && __builtin_isfinite(learned);
+        // A wavefront whose 64 cells all fall back skips the network (the
+        // test is uniform per wavefront; the results are the same).
+        bool use = false;
+        float learned = 0.0f;
+        if (__builtin_amdgcn_ballot_w64(in_range) != 0) {
+            // park the populations in LDS while the network runs (frees registers)
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                pst[q * 256 + tid] = v[q];
+            });
+            wave_lds_sync();  // the previous tile's reads of this wave's staging area are done
+            mlp_stage_inputs(zst, lane, z);
+            wave_lds_sync();
+            const float o = mlp_forward_wave(frag, zst, lane) + P->b3;
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                v[q] = pst[q * 256 + tid];
+            });
+            // a cell whose network activations left the FP16 range (|x| >
+            // 65504) gets a non-finite output: it falls back like an
+            // out-of-range cell
+            learned = P->scale * mlp_softplus(o);
+            use = in_range && __builtin_isfinite(learned);
+        }
         if (use) nut = (C)learned;
         fallbacks += (!use && active) ? 1u : 0u;
     }
     const C tau = tau0 + C(3) * nut;
-    const C itau = C(1) / tau;
+    const C itau = arith_rcp(tau);
 
     // ---- a6: equilibrium + Guo forcing + BGK (shifted) ----------------------
-    // Directions q (odd) and q+1 are opposite: c.u and c.F change sign, so
-    // f~eq = A +- B and F_q = E +- O with A, E even and B, O odd in c:
-    //   A = w (drho + rho (4.5 (c.u)^2 - 1.5 u.u)),  B = 3 w rho (c.u),
-    //   E = pref w (9 (c.u)(c.F) - 3 u.F),           O = 3 pref w (c.F).
+    // Directions q (odd) and q+1 are opposite: c.u and c.F change sign.  The
+    // shifted equilibrium times 1/tau plus the Guo term of the pair splits
+    // into a part even and a part odd in c:
+    //   even = w (K + (c.u) (a1 (c.u) + a2 (c.F))),  odd = w (b1 (c.u) + b2 (c.F)),
+    //   K = (drho - 1.5 rho u.u) / tau - 3 pref u.F,  a1 = 4.5 rho / tau,
+    //   a2 = 9 pref,  b1 = 3 rho / tau,  b2 = 3 pref,  pref = 1 - 1/(2 tau),
+    // then f~_q <- (1 - 1/tau) f~_q + even + odd and f~_{q+1} <- ... + even - odd.
+    // The weight is folded into the per-cell scalars of its class (1/18 for
+    // the axis directions, 1/36 for the edge directions).
     const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
     const C uF = ux * Fx + uy * Fy + uz * Fz;
     const C pref = C(1) - C(0.5) * itau;
     const C om = C(1) - itau;
-    {
-        constexpr C w0 = (C)weight(0);
-        const C feq0 = w0 * (drho - rho * usq15);
-        v[0] = v[0] * om + feq0 * itau - C(3) * pref * w0 * uF;
-    }
+    const C K = itau * (drho - rho * usq15) - C(3) * pref * uF;
+    const C ri = rho * itau;
+    constexpr C w1 = (C)weight(1), w2 = (C)weight(7);
+    const C Kw[2] = {w1 * K, w2 * K};
+    const C a1w[2] = {(w1 * C(4.5)) * ri, (w2 * C(4.5)) * ri};
+    const C a2w[2] = {(w1 * C(9)) * pref, (w2 * C(9)) * pref};
+    const C b1w[2] = {(w1 * C(3)) * ri, (w2 * C(3)) * ri};
+    const C b2w[2] = {(w1 * C(3)) * pref, (w2 * C(3)) * pref};
+    v[0] = v[0] * om + (C)weight(0) * K;
     static_for<(NQ - 1) / 2>([&](auto pc) {
         constexpr int q = 2 * decltype(pc)::value + 1;  // q and q + 1 = opp(q)
         constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
-        constexpr C w = (C)weight(q);
-        C cu = 0, cF = 0;
+        constexpr int cls = weight(q) == weight(1) ? 0 : 1;
+        C cu = C(-0.0), cF = C(-0.0);
         if (cx) { cu += cx > 0 ? ux : -ux; cF += cx > 0 ? Fx : -Fx; }
         if (cy) { cu += cy > 0 ? uy : -uy; cF += cy > 0 ? Fy : -Fy; }
         if (cz) { cu += cz > 0 ? uz : -uz; cF += cz > 0 ? Fz : -Fz; }
-        const C A = w * (drho + rho * (C(4.5) * cu * cu - usq15));
-        const C B = C(3) * w * rho * cu;
-        const C pw = pref * w;
-        const C E = pw * (C(9) * cu * cF - C(3) * uF);
-        const C O = C(3) * pw * cF;
-        const C even = A * itau + E, odd = B * itau + O;
+        const C even = Kw[cls] + cu * (a1w[cls] * cu + a2w[cls] * cF);
+        const C odd = b1w[cls] * cu + b2w[cls] * cF;
         v[q] = v[q] * om + (even + odd);
         v[q + 1] = v[q + 1] * om + (even - odd);
     });
@@ -425,6 +447,10 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
 // Learned closure: persistent blocks keep the network's weight fragments in
 // registers and walk the tiles (linear index it = block + k * grid; with the
 // grid a multiple of 8, every tile of a block stays on the block's XCD).
+// The walk is z-major (row j faster than the z tile): each XCD's contiguous
+// share of the walk then spans every row, so the rows whose cells all fall
+// back to Smagorinsky (and skip the network) are spread evenly over the XCDs
+// and over the blocks, instead of leaving whole XCDs idle.
 template <int ST, int VAR>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 3, ST == ST_F64 ? 2 : 3)))
@@ -443,7 +469,10 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     double imp[3] = {0.0, 0.0, 0.0};
     unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
-        const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
+        const int p = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
+        const int pbx = p % a.nbx, pr = p / a.nbx;
+        const int pj = pr % a.ny, pbz = pr / a.ny;
+        const int tile = (pj * a.nbz + pbz) * a.nbx + pbx;  // the tile order step_tile decodes
         step_tile<ST, true, VAR>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
     // cells that fell back: one atomic per wave
