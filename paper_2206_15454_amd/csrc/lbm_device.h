@@ -57,29 +57,31 @@ enum : int {
     VAR_WIDE = 4           // FLAG_WIDE: population planes of 4 GiB or more (64-bit addresses)
 };
 
-// Population loads and stores.  LBMX_NT_LOAD / LBMX_NT_STORE select the
-// non-temporal (streaming) cache policy.  Measured on MI355X, the default
-// cached policy is faster for both: the neighbour step's x-shifted accesses
-// share cache lines between adjacent tiles, which meet in one XCD's L2.
-#ifndef LBMX_NT_LOAD
-#define LBMX_NT_LOAD 0
+// Population loads and stores of the auxiliary kernels (plain cached accesses).
+template <class T> __device__ __forceinline__ T pop_ld(const T *p) { return *p; }
+template <class T> __device__ __forceinline__ void pop_st(T *p, T v) { *p = v; }
+
+// Cache policy of the step kernel's population accesses: 0 = default, 2 =
+// non-temporal (streaming: the lines are not kept for reuse).  A step
+// touches every population once (2.5 GB per step at 512x128x256 in FP32, far
+// more than the caches).  The local step of the AA pattern and the planes
+// of the neighbour step with c_x = 0 access whole aligned rows; the
+// neighbour step's planes with c_x != 0 are shifted by one cell, so the
+// cache lines at a wavefront's ends are shared with the adjacent
+// wavefront, which finds them in L2 only with the default policy.
+#ifndef LBMX_POLICY_NEIGH_ALIGNED_LD
+#define LBMX_POLICY_NEIGH_ALIGNED_LD 2
 #endif
-#ifndef LBMX_NT_STORE
-#define LBMX_NT_STORE 0
+#ifndef LBMX_POLICY_NEIGH_ALIGNED_ST
+#define LBMX_POLICY_NEIGH_ALIGNED_ST 2
 #endif
-template <class T> __device__ __forceinline__ T pop_ld(const T *p) {
-#if LBMX_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
+#ifndef LBMX_POLICY_NEIGH_SHIFTED_ST
+#define LBMX_POLICY_NEIGH_SHIFTED_ST 0
 #endif
-}
-template <class T> __device__ __forceinline__ void pop_st(T *p, T v) {
-#if LBMX_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+constexpr int kPolicyLocal = 2;
+constexpr int policy_neigh_ld(int q) { return CX[q] == 0 ? LBMX_POLICY_NEIGH_ALIGNED_LD : 0; }
+constexpr int policy_neigh_st(int q) {
+    return CX[q] == 0 ? LBMX_POLICY_NEIGH_ALIGNED_ST : LBMX_POLICY_NEIGH_SHIFTED_ST;
 }
 
 // Storage codecs: T is the element type in HBM, C the arithmetic type.
@@ -167,26 +169,26 @@ template <int ST> struct PopBuf {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(f + q * qs), 0, (int)bytes,
                                                  0x00020000);
     }
-    __device__ __forceinline__ C ld(int q, int x) const {
+    template <int AUX = 0> __device__ __forceinline__ C ld(int q, int x) const {
         const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
         if constexpr (sizeof(T) == 8)
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(q), off, 0, 0)));
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(q), off, 0, AUX)));
         else if constexpr (sizeof(T) == 4)
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(q), off, 0, 0)));
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(q), off, 0, AUX)));
         else
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc(q), off, 0, 0)));
+            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc(q), off, 0, AUX)));
     }
-    __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
+    template <int AUX = 0> __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
         const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
         const T t = CD::enc(v, r);
         if constexpr (sizeof(T) == 8) {
             using R = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(q), 0, 0, 0));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, t), rsrc(q), off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, t), rsrc(q), off, 0, AUX);
         } else if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t), rsrc(q), off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t), rsrc(q), off, 0, AUX);
         } else {
             __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), rsrc(q), off,
-                                                  0, 0);
+                                                  0, AUX);
         }
     }
 };
@@ -196,9 +198,19 @@ template <int ST> struct PopGlobal {
     using C = typename CD::C;
     T *f;
     long long qs;
-    __device__ __forceinline__ C ld(int q, int x) const { return CD::ld(f + q * qs + x); }
-    __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
-        CD::st(f + q * qs + x, v, r);
+    template <int AUX = 0> __device__ __forceinline__ C ld(int q, int x) const {
+        const T *p = f + q * qs + x;
+        if constexpr (AUX != 0)
+            return CD::dec(__builtin_nontemporal_load(p));
+        else
+            return CD::dec(*p);
+    }
+    template <int AUX = 0> __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
+        T *p = f + q * qs + x;
+        if constexpr (AUX != 0)
+            __builtin_nontemporal_store(CD::enc(v, r), p);
+        else
+            *p = CD::enc(v, r);
     }
 };
 

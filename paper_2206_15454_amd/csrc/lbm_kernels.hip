@@ -141,7 +141,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     if (a.parity) {
         static_for<NQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            v[q] = pop.ld(q, self);
+            v[q] = pop.template ld<kPolicyLocal>(q, self);
         });
     } else {
         static_for<NQ>([&](auto qc) {
@@ -151,11 +151,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             if (cy != 0 && (js < 0 || js >= ny) &&
                 (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
                 if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                    v[q] = pop.ld(q, self);  // left this cell towards the wall
+                    v[q] = pop.template ld<policy_neigh_ld(q)>(q, self);  // left this cell towards the wall
                 else  // free slip: left the wall row upstream, moving towards the wall
-                    v[q] = pop.ld(opp(mir(q)), cell(-cx, 0, -cz));
+                    v[q] = pop.template ld<policy_neigh_ld(q)>(opp(mir(q)), cell(-cx, 0, -cz));
             } else {
-                v[q] = pop.ld(opp(q), cell(-cx, -cy, -cz));
+                v[q] = pop.template ld<policy_neigh_ld(q)>(opp(q), cell(-cx, -cy, -cz));
             }
         });
     }
@@ -362,7 +362,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                pop.st(opp(q), self, v[q], rnd(q));
+                pop.template st<kPolicyLocal>(opp(q), self, v[q], rnd(q));
             });
         } else {
             static_for<NQ>([&](auto qc) {
@@ -375,11 +375,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                     // leaving population in the own cell's opposite slot (a
                     // forced-equilibrium boundary never reads it back)
                     if ((jt < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                        pop.st(opp(q), self, v[q], rnd(q));
+                        pop.template st<policy_neigh_st(q)>(opp(q), self, v[q], rnd(q));
                     else
-                        pop.st(mir(q), cell(cx, 0, cz), v[q], rnd(q));
+                        pop.template st<policy_neigh_st(q)>(mir(q), cell(cx, 0, cz), v[q], rnd(q));
                 } else {
-                    pop.st(q, cell(cx, cy, cz), v[q], rnd(q));
+                    pop.template st<policy_neigh_st(q)>(q, cell(cx, cy, cz), v[q], rnd(q));
                 }
             });
         }

@@ -115,6 +115,32 @@ def test_learned_closure_matches_oracle():
     assert normwise(ng, no) <= 5e-2
 
 
+def test_learned_closure_persistent_walk_matches_oracle():
+    """More tiles than the persistent kernel has blocks (256x64x32: 2048
+    tiles of 256 cells), so each block walks several tiles; the closure is
+    restricted to y/h <= 2, so the wavefronts of the upper rows skip the
+    network and fall back to Smagorinsky."""
+    w = inputs.scaled(inputs.C1, 256, 64, 32, canopy_rows=12)
+    o, g = make_pair(w, storage="f64", seed=11)
+    hi = WIDE_HI.copy()
+    hi[6] = 2.0  # y/h = (j + 1/2) / 10: rows j >= 20 fall back
+    blob = blob_with_range(WIDE_LO.copy(), hi, seed=5)
+    o.set_closure(ref.MLP(blob))
+    g.set_closure(blob)
+    o.step(1)
+    g.step(1)
+    _, uo, no, do = o.moments()
+    _, ug, ng, dg = g.moments()
+    upper = np.zeros(w.shape, dtype=bool)
+    upper[:, 20:, :] = True
+    assert do["mlp_fallback"] == dg["mlp_fallback"] == upper.sum()
+    assert normwise(ng[upper], no[upper]) <= 1e-12
+    e_mlp = normwise(ng[~upper], no[~upper])
+    print("persistent walk: learned nu_t normwise error", e_mlp)
+    assert e_mlp <= 3e-2
+    assert normwise(ug, uo) <= 1e-6
+
+
 def test_closure_interval_matches_oracle():
     """Learned closure evaluated every 3 steps: the steps in between reuse
     the nu_t of the last evaluation, on the GPU as in the oracle."""
