@@ -32,6 +32,7 @@ struct lbm_ctx {
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;
     bool force_wide = false;  // 64-bit population addresses even for small planes
+    bool streaming = false;   // non-temporal accesses on aligned rows (FLAG_STREAMING)
     // device memory
     void *base = nullptr;
     bool owns = false;
@@ -244,6 +245,10 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->ntiles = c->tpp * p->ny;
     if (const char *e = std::getenv("LBMX_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     if (const char *e = std::getenv("LBMX_WIDE")) c->force_wide = std::atoi(e) != 0;
+    // streaming (non-temporal) accesses where rows are whole 128-byte lines
+    // (the planes start on 256-byte boundaries); LBMX_STREAMING=0/1 overrides
+    c->streaming = ((long long)p->nx * (long long)c->elt) % 128 == 0;
+    if (const char *e = std::getenv("LBMX_STREAMING")) c->streaming = std::atoi(e) != 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LBM_EDEVICE;
@@ -454,6 +459,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->p.g[1] == 0.0 && c->p.g[2] == 0.0 && !c->vector_drag) base_flags |= FLAG_IMPULSE_X;
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
+    if (c->streaming) base_flags |= FLAG_STREAMING;
     // planes of 4 GiB or more cannot be addressed by a buffer resource
     // (LBMX_WIDE=1 forces the 64-bit path, for tests)
     if ((unsigned long long)c->qs * c->elt >= (1ULL << 32) || c->force_wide)

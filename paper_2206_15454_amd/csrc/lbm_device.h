@@ -47,14 +47,16 @@ enum : int {
     FLAG_NUT_IN = 128,     // nu_t read from the moments' nu_t plane (learned closure reused)
     FLAG_NUT_OUT = 256,    // nu_t written to that plane on every step of the launch
     FLAG_WIDE = 512,       // a population plane has 2^32 bytes or more
-    FLAG_IMPULSE_X = 1024  // g_y = g_z = 0 and x-only drag: the y, z forces are 0
+    FLAG_IMPULSE_X = 1024, // g_y = g_z = 0 and x-only drag: the y, z forces are 0
+    FLAG_STREAMING = 2048  // rows start on cache lines: aligned accesses are non-temporal
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
 enum : int {
     VAR_FOREST = 1,        // FLAG_FOREST
     VAR_NUT_IN = 2,        // FLAG_NUT_IN
-    VAR_WIDE = 4           // FLAG_WIDE: population planes of 4 GiB or more (64-bit addresses)
+    VAR_WIDE = 4,          // FLAG_WIDE: population planes of 4 GiB or more (64-bit addresses)
+    VAR_STREAM = 8         // FLAG_STREAMING (plain step kernel, buffer addressing only)
 };
 
 // Population loads and stores of the auxiliary kernels (plain cached accesses).
@@ -64,25 +66,16 @@ template <class T> __device__ __forceinline__ void pop_st(T *p, T v) { *p = v; }
 // Cache policy of the step kernel's population accesses: 0 = default, 2 =
 // non-temporal (streaming: the lines are not kept for reuse).  A step
 // touches every population once (2.5 GB per step at 512x128x256 in FP32, far
-// more than the caches).  The local step of the AA pattern and the planes
-// of the neighbour step with c_x = 0 access whole aligned rows; the
-// neighbour step's planes with c_x != 0 are shifted by one cell, so the
-// cache lines at a wavefront's ends are shared with the adjacent
-// wavefront, which finds them in L2 only with the default policy.
-#ifndef LBMX_POLICY_NEIGH_ALIGNED_LD
-#define LBMX_POLICY_NEIGH_ALIGNED_LD 2
-#endif
-#ifndef LBMX_POLICY_NEIGH_ALIGNED_ST
-#define LBMX_POLICY_NEIGH_ALIGNED_ST 2
-#endif
-#ifndef LBMX_POLICY_NEIGH_SHIFTED_ST
-#define LBMX_POLICY_NEIGH_SHIFTED_ST 0
-#endif
-constexpr int kPolicyLocal = 2;
-constexpr int policy_neigh_ld(int q) { return CX[q] == 0 ? LBMX_POLICY_NEIGH_ALIGNED_LD : 0; }
-constexpr int policy_neigh_st(int q) {
-    return CX[q] == 0 ? LBMX_POLICY_NEIGH_ALIGNED_ST : LBMX_POLICY_NEIGH_SHIFTED_ST;
-}
+// more than the caches).  With FLAG_STREAMING (set when a row of the grid is
+// a whole number of 128-byte lines) the accesses that cover whole aligned
+// rows stream: every access of the local step of the AA pattern, and the
+// neighbour step's planes with c_x = 0.  The neighbour step's planes with
+// c_x != 0 are shifted by one cell: the lines at a wavefront's ends are
+// shared with the adjacent wavefront, which finds them in L2 only with the
+// default policy.  Rows that are not whole lines share their end lines with
+// the next row, which a later block reads: they keep the default policy.
+template <bool STREAM> constexpr int policy_local() { return STREAM ? 2 : 0; }
+template <bool STREAM> constexpr int policy_neigh(int q) { return STREAM && CX[q] == 0 ? 2 : 0; }
 
 // Storage codecs: T is the element type in HBM, C the arithmetic type.
 // Stored values are shifted populations f_q - w_q.  st() takes 32 random bits

@@ -138,27 +138,41 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     if constexpr ((VAR & VAR_FOREST) != 0) fidx = a.fidx[self];
 
     C v[NQ];
-    if (a.parity) {
-        static_for<NQ>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            v[q] = pop.template ld<kPolicyLocal>(q, self);
-        });
-    } else {
-        static_for<NQ>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
-            const int js = j - cy;
-            if (cy != 0 && (js < 0 || js >= ny) &&
-                (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
-                if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                    v[q] = pop.template ld<policy_neigh_ld(q)>(q, self);  // left this cell towards the wall
-                else  // free slip: left the wall row upstream, moving towards the wall
-                    v[q] = pop.template ld<policy_neigh_ld(q)>(opp(mir(q)), cell(-cx, 0, -cz));
-            } else {
-                v[q] = pop.template ld<policy_neigh_ld(q)>(opp(q), cell(-cx, -cy, -cz));
-            }
-        });
-    }
+    auto load = [&](auto stream) {
+        constexpr bool S = decltype(stream)::value;
+        if (a.parity) {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                v[q] = pop.template ld<policy_local<S>()>(q, self);
+            });
+        } else {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+                constexpr int pol = policy_neigh<S>(q);
+                const int js = j - cy;
+                if (cy != 0 && (js < 0 || js >= ny) &&
+                    (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
+                    if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
+                        v[q] = pop.template ld<pol>(q, self);  // left this cell towards the wall
+                    else  // free slip: left the wall row upstream, moving towards the wall
+                        v[q] = pop.template ld<pol>(opp(mir(q)), cell(-cx, 0, -cz));
+                } else {
+                    v[q] = pop.template ld<pol>(opp(q), cell(-cx, -cy, -cz));
+                }
+            });
+        }
+    };
+    // the plain step kernel has the policy as a compile-time variant; the
+    // learned-closure kernel branches on the flag (uniform per launch)
+    constexpr bool kStream = (VAR & VAR_STREAM) != 0;
+    [[maybe_unused]] const bool streaming = LEARNED ? (a.flags & FLAG_STREAMING) != 0 : kStream;
+    if constexpr (!LEARNED)
+        load(std::bool_constant<kStream>{});
+    else if (streaming)
+        load(std::true_type{});
+    else
+        load(std::false_type{});
     if ((j == 0 && a.bc_lo == BC_EQUILIBRIUM) || (j == ny - 1 && a.bc_hi == BC_EQUILIBRIUM)) {
         static_for<NQ>([&](auto qc) {  // uniform per block (one row per block)
             constexpr int q = decltype(qc)::value;
@@ -358,16 +372,18 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         }
         return (q & 1) ? rpair : (rpair >> 16);
     };
-    if (active) {
+    auto store = [&](auto stream) {
+        constexpr bool S = decltype(stream)::value;
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                pop.template st<kPolicyLocal>(opp(q), self, v[q], rnd(q));
+                pop.template st<policy_local<S>()>(opp(q), self, v[q], rnd(q));
             });
         } else {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
+                constexpr int pol = policy_neigh<S>(q);
                 const int jt = j + cy;
                 if (cy != 0 && (jt < 0 || jt >= ny) &&
                     (jt < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
@@ -375,14 +391,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                     // leaving population in the own cell's opposite slot (a
                     // forced-equilibrium boundary never reads it back)
                     if ((jt < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                        pop.template st<policy_neigh_st(q)>(opp(q), self, v[q], rnd(q));
+                        pop.template st<pol>(opp(q), self, v[q], rnd(q));
                     else
-                        pop.template st<policy_neigh_st(q)>(mir(q), cell(cx, 0, cz), v[q], rnd(q));
+                        pop.template st<pol>(mir(q), cell(cx, 0, cz), v[q], rnd(q));
                 } else {
-                    pop.template st<policy_neigh_st(q)>(q, cell(cx, cy, cz), v[q], rnd(q));
+                    pop.template st<pol>(q, cell(cx, cy, cz), v[q], rnd(q));
                 }
             });
         }
+    };
+    if (active) {
+        if constexpr (!LEARNED)
+            store(std::bool_constant<kStream>{});
+        else if (streaming)
+            store(std::true_type{});
+        else
+            store(std::false_type{});
     }
 
     // ---- a8: moments of this collision -------------------------------------
@@ -716,10 +740,13 @@ __global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 // compile-time variant from the launch flags
+// (streaming only with buffer addressing: the 64-bit path keeps the default
+// cache policy)
 #define LBMX_VARIANT(flags, CALL)                                      \
     switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
             ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0) |                 \
-            ((flags) & FLAG_WIDE ? VAR_WIDE : 0)) {                    \
+            ((flags) & FLAG_WIDE ? VAR_WIDE                            \
+                                 : ((flags) & FLAG_STREAMING ? VAR_STREAM : 0))) { \
     case 0: { constexpr int V = 0; CALL; } break;                      \
     case 1: { constexpr int V = 1; CALL; } break;                      \
     case 2: { constexpr int V = 2; CALL; } break;                      \
@@ -727,7 +754,11 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
     case 4: { constexpr int V = 4; CALL; } break;                      \
     case 5: { constexpr int V = 5; CALL; } break;                      \
     case 6: { constexpr int V = 6; CALL; } break;                      \
-    default: { constexpr int V = 7; CALL; } break;                     \
+    case 7: { constexpr int V = 7; CALL; } break;                      \
+    case 8: { constexpr int V = 8; CALL; } break;                      \
+    case 9: { constexpr int V = 9; CALL; } break;                      \
+    case 10: { constexpr int V = 10; CALL; } break;                    \
+    default: { constexpr int V = 11; CALL; } break;                    \
     }
 
 // the learned-closure kernel's variants (it computes nu_t: never VAR_NUT_IN)

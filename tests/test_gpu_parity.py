@@ -192,6 +192,21 @@ def test_buffer_and_64bit_addressing_agree(monkeypatch, storage):
     np.testing.assert_array_equal(res[1], res[0])
 
 
+@pytest.mark.parametrize("storage,nx", [("f32", 64), ("bf16sr", 128), ("f64", 70)])
+def test_streaming_cache_policy_changes_nothing(monkeypatch, storage, nx):
+    """Rows of whole 128-byte lines use non-temporal accesses (LBMX_STREAMING
+    forces the policy on or off): a cache hint, so the populations are
+    bit-identical, both AA parities, walls included."""
+    w = inputs.scaled(inputs.C1, nx, 9, 6, canopy_rows=4)
+    res = []
+    for stream in ("0", "1"):
+        monkeypatch.setenv("LBMX_STREAMING", stream)
+        _, g = make_pair(w, storage=storage, seed=8)
+        g.step(7)
+        res.append(g.get_f())
+    np.testing.assert_array_equal(res[1], res[0])
+
+
 def test_errors_and_state_machine():
     from paper_2206_15454_amd import lbm
 
