@@ -460,9 +460,9 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
     if (c->streaming) base_flags |= FLAG_STREAMING;
-    // planes of 4 GiB or more cannot be addressed by a buffer resource
+    // arrays too large for buffer resources take 64-bit addresses
     // (LBMX_WIDE=1 forces the 64-bit path, for tests)
-    if ((unsigned long long)c->qs * c->elt >= (1ULL << 32) || c->force_wide)
+    if (pop_wide(c->p.storage, (unsigned long long)c->qs * c->elt) || c->force_wide)
         base_flags |= FLAG_WIDE;
     for (int64_t s = 0; s < nsteps; ++s) {
         a.parity = c->parity;

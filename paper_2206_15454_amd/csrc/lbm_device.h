@@ -46,7 +46,7 @@ enum : int {
     FLAG_FOREST = 64,      // per-cell LAD: ftab[fidx[cell]] instead of lad[row]
     FLAG_NUT_IN = 128,     // nu_t read from the moments' nu_t plane (learned closure reused)
     FLAG_NUT_OUT = 256,    // nu_t written to that plane on every step of the launch
-    FLAG_WIDE = 512,       // a population plane has 2^32 bytes or more
+    FLAG_WIDE = 512,       // the population array has 2^32 bytes or more
     FLAG_IMPULSE_X = 1024, // g_y = g_z = 0 and x-only drag: the y, z forces are 0
     FLAG_STREAMING = 2048  // rows start on cache lines: aligned accesses are non-temporal
 };
@@ -55,8 +55,8 @@ enum : int {
 enum : int {
     VAR_FOREST = 1,        // FLAG_FOREST
     VAR_NUT_IN = 2,        // FLAG_NUT_IN
-    VAR_WIDE = 4,          // FLAG_WIDE: population planes of 4 GiB or more (64-bit addresses)
-    VAR_STREAM = 8         // FLAG_STREAMING (plain step kernel, buffer addressing only)
+    VAR_WIDE = 4,          // FLAG_WIDE: population arrays of 4 GiB or more (64-bit addresses)
+    VAR_STREAM = 8         // FLAG_STREAMING (plain step kernel)
 };
 
 // Population loads and stores of the auxiliary kernels (plain cached accesses).
@@ -146,51 +146,98 @@ template <> struct Codec<ST_BF16SR> {
 };
 
 // Population access of the step kernel, by direction plane q and cell index.
-// PopBuf: buffer resources, one per plane (base f + q qs, the plane's size),
-// with a 32-bit byte offset per cell: the plane address is scalar work and an
-// access costs one 32-bit multiply-add; an access past the plane reads 0 and
-// a store there is dropped.  Needs plane bytes < 2^32.  PopGlobal: plain
-// 64-bit addresses, for larger planes.
-template <int ST> struct PopBuf {
+// Three forms, chosen per storage type and size (measured on MI355X):
+// PopArray: one buffer resource for the whole population array, built once in
+// scalar registers; the plane enters as the scalar offset q * plane bytes and
+// the cell as a 32-bit byte offset, so an access costs no scalar work beyond
+// the plane offset.  Needs all planes together below 2^32 bytes.  Used for
+// the 16-bit and FP64 storage types (16-bit: 5 % faster than PopPlanes).
+// PopPlanes: one buffer resource per plane (base f + q qs, the plane's size)
+// and a 32-bit byte offset per cell.  Needs plane bytes below 2^32.  Used for
+// FP32 (2 % faster than PopArray there).
+// PopGlobal: plain 64-bit addresses, for larger arrays.
+template <int ST> struct PopArray {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
-    const T *f;
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t plane;  // bytes per plane (the plane stride)
+    __device__ __forceinline__ void init(T *f, long long qs) {
+        plane = (uint32_t)(qs * (long long)sizeof(T));
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(plane * (uint32_t)NQ), 0x00020000);
+    }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(int) const { return rsrc; }
+    __device__ __forceinline__ uint32_t so(int q) const { return (uint32_t)q * plane; }
+};
+template <int ST> struct PopPlanes {
+    using CD = Codec<ST>;
+    using T = typename CD::T;
+    using C = typename CD::C;
+    T *f;
     long long qs;
     uint32_t bytes;  // plane size in bytes
-    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int q) const {
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(f + q * qs), 0, (int)bytes,
-                                                 0x00020000);
+    __device__ __forceinline__ void init(T *f_, long long qs_) {
+        f = f_;
+        qs = qs_;
+        bytes = (uint32_t)(qs * (long long)sizeof(T));
     }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(int q) const {
+        return __builtin_amdgcn_make_buffer_rsrc(f + q * qs, 0, (int)bytes, 0x00020000);
+    }
+    __device__ __forceinline__ uint32_t so(int) const { return 0u; }
+};
+// loads and stores through a buffer resource (PopArray or PopPlanes)
+template <class Base> struct PopBuf : Base {
+    using CD = typename Base::CD;
+    using T = typename CD::T;
+    using C = typename CD::C;
     template <int AUX = 0> __device__ __forceinline__ C ld(int q, int x) const {
         const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
         if constexpr (sizeof(T) == 8)
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(q), off, 0, AUX)));
+            return CD::dec(__builtin_bit_cast(
+                T, __builtin_amdgcn_raw_buffer_load_b64(this->rs(q), off, this->so(q), AUX)));
         else if constexpr (sizeof(T) == 4)
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(q), off, 0, AUX)));
+            return CD::dec(__builtin_bit_cast(
+                T, __builtin_amdgcn_raw_buffer_load_b32(this->rs(q), off, this->so(q), AUX)));
         else
-            return CD::dec(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc(q), off, 0, AUX)));
+            return CD::dec(__builtin_bit_cast(
+                T, __builtin_amdgcn_raw_buffer_load_b16(this->rs(q), off, this->so(q), AUX)));
     }
     template <int AUX = 0> __device__ __forceinline__ void st(int q, int x, C v, uint32_t r) const {
         const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
         const T t = CD::enc(v, r);
         if constexpr (sizeof(T) == 8) {
-            using R = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(q), 0, 0, 0));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, t), rsrc(q), off, 0, AUX);
+            using R = decltype(__builtin_amdgcn_raw_buffer_load_b64(this->rs(q), 0, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, t), this->rs(q), off,
+                                                  this->so(q), AUX);
         } else if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t), rsrc(q), off, 0, AUX);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t), this->rs(q), off,
+                                                  this->so(q), AUX);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), rsrc(q), off,
-                                                  0, AUX);
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), this->rs(q),
+                                                  off, this->so(q), AUX);
         }
     }
 };
+// the buffer form of a storage type, and whether a population array of
+// 'plane_bytes' per plane needs 64-bit addresses instead
+constexpr bool pop_planes(int st) { return st == ST_F32; }
+template <int ST>
+using PopBufOf = PopBuf<std::conditional_t<pop_planes(ST), PopPlanes<ST>, PopArray<ST>>>;
+constexpr bool pop_wide(int st, unsigned long long plane_bytes) {
+    return (pop_planes(st) ? plane_bytes : plane_bytes * NQ) >= (1ULL << 32);
+}
+
 template <int ST> struct PopGlobal {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
     T *f;
     long long qs;
+    __device__ __forceinline__ void init(T *f_, long long qs_) {
+        f = f_;
+        qs = qs_;
+    }
     template <int AUX = 0> __device__ __forceinline__ C ld(int q, int x) const {
         const T *p = f + q * qs + x;
         if constexpr (AUX != 0)

@@ -74,16 +74,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
-    // population planes: buffer resources, or 64-bit addresses for planes of
-    // 4 GiB and more
-    // (the learned-closure kernel keeps 64-bit addresses: its scalar
-    // registers are taken by the network's fragments)
-    using Pop = std::conditional_t<(VAR & VAR_WIDE) != 0 || LEARNED, PopGlobal<ST>, PopBuf<ST>>;
+    // population array: buffer resources, or 64-bit addresses for arrays
+    // too large for them (the learned-closure kernel keeps 64-bit addresses:
+    // its scalar registers are taken by the network's fragments)
+    using Pop = std::conditional_t<(VAR & VAR_WIDE) != 0 || LEARNED, PopGlobal<ST>, PopBufOf<ST>>;
     Pop pop;
-    pop.f = static_cast<T *>(a.f);
-    pop.qs = a.qs;
-    if constexpr ((VAR & VAR_WIDE) == 0 && !LEARNED)
-        pop.bytes = (uint32_t)(a.qs * (long long)sizeof(T));
+    pop.init(static_cast<T *>(a.f), a.qs);
     // kernel scalars in the arithmetic type (FP32 copies avoid per-thread conversions)
     constexpr bool F32 = std::is_same_v<C, float>;
     auto sc = [](double d, float fl) -> C {
@@ -740,13 +736,11 @@ __global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 // compile-time variant from the launch flags
-// (streaming only with buffer addressing: the 64-bit path keeps the default
-// cache policy)
 #define LBMX_VARIANT(flags, CALL)                                      \
     switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
             ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0) |                 \
-            ((flags) & FLAG_WIDE ? VAR_WIDE                            \
-                                 : ((flags) & FLAG_STREAMING ? VAR_STREAM : 0))) { \
+            ((flags) & FLAG_WIDE ? VAR_WIDE : 0) |                     \
+            ((flags) & FLAG_STREAMING ? VAR_STREAM : 0)) {             \
     case 0: { constexpr int V = 0; CALL; } break;                      \
     case 1: { constexpr int V = 1; CALL; } break;                      \
     case 2: { constexpr int V = 2; CALL; } break;                      \
@@ -758,7 +752,11 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
     case 8: { constexpr int V = 8; CALL; } break;                      \
     case 9: { constexpr int V = 9; CALL; } break;                      \
     case 10: { constexpr int V = 10; CALL; } break;                    \
-    default: { constexpr int V = 11; CALL; } break;                    \
+    case 11: { constexpr int V = 11; CALL; } break;                    \
+    case 12: { constexpr int V = 12; CALL; } break;                    \
+    case 13: { constexpr int V = 13; CALL; } break;                    \
+    case 14: { constexpr int V = 14; CALL; } break;                    \
+    default: { constexpr int V = 15; CALL; } break;                    \
     }
 
 // the learned-closure kernel's variants (it computes nu_t: never VAR_NUT_IN)

@@ -179,9 +179,9 @@ def test_tile_width_does_not_change_fp64_results(monkeypatch):
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
 def test_buffer_and_64bit_addressing_agree(monkeypatch, storage):
-    """The step addresses populations through buffer resources (planes below
-    4 GiB) or 64-bit pointers (larger planes; forced here with LBMX_WIDE):
-    bit-identical populations, both AA parities, walls and a forest."""
+    """The step addresses populations through one buffer resource (arrays
+    below 4 GiB) or 64-bit pointers (larger arrays; forced here with
+    LBMX_WIDE): bit-identical populations, both AA parities, walls."""
     w = inputs.scaled(inputs.C1, 70, 9, 6, canopy_rows=4)
     res = []
     for wide in ("0", "1"):
