@@ -431,6 +431,9 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.nz = c->p.nz;
     a.nbx = c->nbx;
     a.nbz = c->nbz;
+    div_magic((uint32_t)a.nbx, &a.m_nbx, &a.s_nbx);
+    div_magic((uint32_t)a.nbz, &a.m_nbz, &a.s_nbz);
+    div_magic((uint32_t)c->p.ny, &a.m_ny, &a.s_ny);
     a.ntiles = c->ntiles;
     a.bc_lo = c->p.bc_ylo;
     a.bc_hi = c->p.bc_yhi;

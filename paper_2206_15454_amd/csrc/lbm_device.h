@@ -277,6 +277,9 @@ struct StepArgs {
     long long qs;
     int nx, ny, nz;
     int nbx, nbz;     // tiles per row (x) and per column (z); tile = BX x 1 x BZ cells
+    // division by nbx, nbz and ny as multiply and shift (div_magic)
+    uint32_t m_nbx, m_nbz, m_ny;
+    int s_nbx, s_nbz, s_ny;
     int ntiles;       // nbx * nbz * ny = grid size
     int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
     int bc_lo, bc_hi;
@@ -317,6 +320,19 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int q = n >> 3, r = n & 7;
     const int x = b & 7, local = b >> 3;
     return x * q + (x < r ? x : r) + local;
+}
+
+// Division of 0 <= n < 2^31 by a constant d >= 1 as n * m >> s (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994,
+// Thm. 4.2 with N = 31): l = ceil(log2 d), m = ceil(2^(31+l) / d) < 2^32.
+inline void div_magic(uint32_t d, uint32_t *m, int *s) {
+    int l = 0;
+    while ((1ULL << l) < d) ++l;
+    *s = 31 + l;
+    *m = (uint32_t)(((1ULL << (31 + l)) + d - 1) / d);
+}
+__device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t m, int s) {
+    return (uint32_t)(((unsigned long long)n * m) >> s);
 }
 
 // Launchers (defined in lbm_kernels.hip).

@@ -86,10 +86,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         if constexpr (F32) return fl; else return (C)d;
     };
 
-    const int bx = tile % a.nbx;
-    const int rest = tile / a.nbx;
-    const int bz = rest % a.nbz;
-    const int j = rest / a.nbz;  // the whole block lies in row j
+    const int rest = (int)div_by((uint32_t)tile, a.m_nbx, a.s_nbx);
+    const int bx = tile - rest * a.nbx;
+    const int j = (int)div_by((uint32_t)rest, a.m_nbz, a.s_nbz);  // the whole block lies in row j
+    const int bz = rest - j * a.nbz;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int i = bx * (int)blockDim.x + (int)threadIdx.x;
     const int k = bz * (int)blockDim.y + (int)threadIdx.y;
@@ -134,12 +134,20 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     if constexpr ((VAR & VAR_FOREST) != 0) fidx = a.fidx[self];
 
     C v[NQ];
+    // rows whose neighbour step crosses a non-periodic y boundary (uniform per
+    // block); the other rows stream without per-direction wall tests
+    const bool wall_row = (j == 0 && a.bc_lo != BC_PERIODIC) || (j == ny - 1 && a.bc_hi != BC_PERIODIC);
     auto load = [&](auto stream) {
         constexpr bool S = decltype(stream)::value;
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 v[q] = pop.template ld<policy_local<S>()>(q, self);
+            });
+        } else if (!wall_row) {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                v[q] = pop.template ld<policy_neigh<S>(q)>(opp(q), cell(-CX[q], -CY[q], -CZ[q]));
             });
         } else {
             static_for<NQ>([&](auto qc) {
@@ -375,6 +383,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                 constexpr int q = decltype(qc)::value;
                 pop.template st<policy_local<S>()>(opp(q), self, v[q], rnd(q));
             });
+        } else if (!wall_row) {
+            static_for<NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                pop.template st<policy_neigh<S>(q)>(q, cell(CX[q], CY[q], CZ[q]), v[q], rnd(q));
+            });
         } else {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
@@ -490,8 +503,8 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int p = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        const int pbx = p % a.nbx, pr = p / a.nbx;
-        const int pj = pr % a.ny, pbz = pr / a.ny;
+        const int pr = (int)div_by((uint32_t)p, a.m_nbx, a.s_nbx), pbx = p - pr * a.nbx;
+        const int pbz = (int)div_by((uint32_t)pr, a.m_ny, a.s_ny), pj = pr - pbz * a.ny;
         const int tile = (pj * a.nbz + pbz) * a.nbx + pbx;  // the tile order step_tile decodes
         step_tile<ST, true, VAR>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
