@@ -33,6 +33,7 @@ struct lbm_ctx {
     bool xcd_remap = true;
     bool force_wide = false;  // 64-bit population addresses even for small planes
     bool streaming = false;   // non-temporal accesses on aligned rows (FLAG_STREAMING)
+    bool memorder = false;    // tiles in memory order (FLAG_MEMORDER)
     // device memory
     void *base = nullptr;
     bool owns = false;
@@ -249,6 +250,13 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     // (the planes start on 256-byte boundaries); LBMX_STREAMING=0/1 overrides
     c->streaming = ((long long)p->nx * (long long)c->elt) % 128 == 0;
     if (const char *e = std::getenv("LBMX_STREAMING")) c->streaming = std::atoi(e) != 0;
+    // tile order: the tiles that run at the same time span the fewest pages in
+    // memory order; the row-major order measured faster for planes of up to
+    // 64 MiB (512x128x256 in FP32 and 16-bit), memory order for 128 MiB and
+    // more (FP64 at that size, every type at 1024x256x512); the switch is at
+    // 96 MiB.  LBMX_TILE_ORDER=0/1 overrides.
+    c->memorder = (unsigned long long)c->qs * c->elt > (96ULL << 20);
+    if (const char *e = std::getenv("LBMX_TILE_ORDER")) c->memorder = std::atoi(e) != 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LBM_EDEVICE;
@@ -463,6 +471,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
     if (c->streaming) base_flags |= FLAG_STREAMING;
+    if (c->memorder) base_flags |= FLAG_MEMORDER;
     // arrays too large for buffer resources take 64-bit addresses
     // (LBMX_WIDE=1 forces the 64-bit path, for tests)
     if (pop_wide(c->p.storage, (unsigned long long)c->qs * c->elt) || c->force_wide)

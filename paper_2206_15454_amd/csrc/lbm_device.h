@@ -48,7 +48,8 @@ enum : int {
     FLAG_NUT_OUT = 256,    // nu_t written to that plane on every step of the launch
     FLAG_WIDE = 512,       // the population array has 2^32 bytes or more
     FLAG_IMPULSE_X = 1024, // g_y = g_z = 0 and x-only drag: the y, z forces are 0
-    FLAG_STREAMING = 2048  // rows start on cache lines: aligned accesses are non-temporal
+    FLAG_STREAMING = 2048, // rows start on cache lines: aligned accesses are non-temporal
+    FLAG_MEMORDER = 4096   // tiles numbered in memory order (planes above 96 MiB)
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
@@ -147,27 +148,34 @@ template <> struct Codec<ST_BF16SR> {
 
 // Population access of the step kernel, by direction plane q and cell index.
 // Three forms, chosen per storage type and size (measured on MI355X):
-// PopArray: one buffer resource for the whole population array, built once in
-// scalar registers; the plane enters as the scalar offset q * plane bytes and
-// the cell as a 32-bit byte offset, so an access costs no scalar work beyond
-// the plane offset.  Needs all planes together below 2^32 bytes.  Used for
-// the 16-bit and FP64 storage types (16-bit: 5 % faster than PopPlanes).
+// PopArray: two buffer resources for the population array (planes 0-9 and
+// 10-18), built once in scalar registers; the plane enters as the scalar
+// offset (q - first plane of its half) * plane bytes and the cell as a 32-bit
+// byte offset, so an access costs no scalar work beyond the plane offset.
+// Needs 10 planes below 2^32 bytes.  Used for the 16-bit and FP64 storage
+// types (16-bit: 5 % faster than PopPlanes).
 // PopPlanes: one buffer resource per plane (base f + q qs, the plane's size)
 // and a 32-bit byte offset per cell.  Needs plane bytes below 2^32.  Used for
 // FP32 (2 % faster than PopArray there).
 // PopGlobal: plain 64-bit addresses, for larger arrays.
+constexpr int kArraySplit = 10;  // PopArray: planes 0-9 and 10-18, one resource each
 template <int ST> struct PopArray {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
-    __amdgpu_buffer_rsrc_t rsrc;
+    static constexpr int kSplit = kArraySplit;
+    __amdgpu_buffer_rsrc_t r0, r1;
     uint32_t plane;  // bytes per plane (the plane stride)
     __device__ __forceinline__ void init(T *f, long long qs) {
         plane = (uint32_t)(qs * (long long)sizeof(T));
-        rsrc = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(plane * (uint32_t)NQ), 0x00020000);
+        r0 = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(plane * (uint32_t)kSplit), 0x00020000);
+        r1 = __builtin_amdgcn_make_buffer_rsrc(f + kSplit * qs, 0,
+                                               (int)(plane * (uint32_t)(NQ - kSplit)), 0x00020000);
     }
-    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(int) const { return rsrc; }
-    __device__ __forceinline__ uint32_t so(int q) const { return (uint32_t)q * plane; }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(int q) const { return q < kSplit ? r0 : r1; }
+    __device__ __forceinline__ uint32_t so(int q) const {
+        return (uint32_t)(q < kSplit ? q : q - kSplit) * plane;
+    }
 };
 template <int ST> struct PopPlanes {
     using CD = Codec<ST>;
@@ -225,7 +233,7 @@ constexpr bool pop_planes(int st) { return st == ST_F32; }
 template <int ST>
 using PopBufOf = PopBuf<std::conditional_t<pop_planes(ST), PopPlanes<ST>, PopArray<ST>>>;
 constexpr bool pop_wide(int st, unsigned long long plane_bytes) {
-    return (pop_planes(st) ? plane_bytes : plane_bytes * NQ) >= (1ULL << 32);
+    return (pop_planes(st) ? plane_bytes : plane_bytes * kArraySplit) >= (1ULL << 32);
 }
 
 template <int ST> struct PopGlobal {

@@ -86,10 +86,20 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         if constexpr (F32) return fl; else return (C)d;
     };
 
+    // tile numbering, x tile fastest: row-major (then the z tile, then the row
+    // j) or, with FLAG_MEMORDER and in the learned-closure kernel, memory
+    // order (then the row j, then the z tile), in which the tiles that run at
+    // the same time touch neighbouring rows of each plane
     const int rest = (int)div_by((uint32_t)tile, a.m_nbx, a.s_nbx);
     const int bx = tile - rest * a.nbx;
-    const int j = (int)div_by((uint32_t)rest, a.m_nbz, a.s_nbz);  // the whole block lies in row j
-    const int bz = rest - j * a.nbz;
+    int j, bz;  // the whole block lies in row j
+    if (LEARNED || (a.flags & FLAG_MEMORDER) != 0) {
+        bz = (int)div_by((uint32_t)rest, a.m_ny, a.s_ny);
+        j = rest - bz * a.ny;
+    } else {
+        j = (int)div_by((uint32_t)rest, a.m_nbz, a.s_nbz);
+        bz = rest - j * a.nbz;
+    }
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int i = bx * (int)blockDim.x + (int)threadIdx.x;
     const int k = bz * (int)blockDim.y + (int)threadIdx.y;
@@ -480,10 +490,9 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
 // Learned closure: persistent blocks keep the network's weight fragments in
 // registers and walk the tiles (linear index it = block + k * grid; with the
 // grid a multiple of 8, every tile of a block stays on the block's XCD).
-// The walk is z-major (row j faster than the z tile): each XCD's contiguous
-// share of the walk then spans every row, so the rows whose cells all fall
-// back to Smagorinsky (and skip the network) are spread evenly over the XCDs
-// and over the blocks, instead of leaving whole XCDs idle.
+// The walk is in the memory order of the tiles: each XCD's contiguous share
+// spans every row j, so the rows whose cells all fall back to Smagorinsky
+// (and skip the network) are spread evenly over the XCDs and the blocks.
 template <int ST, int VAR>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 3, ST == ST_F64 ? 2 : 3)))
@@ -502,10 +511,7 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     double imp[3] = {0.0, 0.0, 0.0};
     unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
-        const int p = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        const int pr = (int)div_by((uint32_t)p, a.m_nbx, a.s_nbx), pbx = p - pr * a.nbx;
-        const int pbz = (int)div_by((uint32_t)pr, a.m_ny, a.s_ny), pj = pr - pbz * a.ny;
-        const int tile = (pj * a.nbz + pbz) * a.nbx + pbx;  // the tile order step_tile decodes
+        const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
         step_tile<ST, true, VAR>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
     // cells that fell back: one atomic per wave
