@@ -32,7 +32,8 @@ PAPER_MLUPS = {"paper-abl-200x80x160-case1": 83.7, "paper-abl-250x100x200-case1"
                "paper-abl-350x140x280-case1": 97.7}
 BYTES_PER_ELT = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2, "bf16sr": 2}
 KERNEL_SOURCES = ("paper_2206_15454_amd/csrc/lbm_kernels.hip",
-                  "paper_2206_15454_amd/csrc/lbm_device.h")
+                  "paper_2206_15454_amd/csrc/lbm_device.h",
+                  "paper_2206_15454_amd/csrc/lbm_api.hip")
 
 
 def kernel_hash():

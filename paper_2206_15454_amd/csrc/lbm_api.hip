@@ -251,11 +251,13 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->streaming = ((long long)p->nx * (long long)c->elt) % 128 == 0;
     if (const char *e = std::getenv("LBMX_STREAMING")) c->streaming = std::atoi(e) != 0;
     // tile order: the tiles that run at the same time span the fewest pages in
-    // memory order; the row-major order measured faster for planes of up to
-    // 64 MiB (512x128x256 in FP32 and 16-bit), memory order for 128 MiB and
-    // more (FP64 at that size, every type at 1024x256x512); the switch is at
-    // 96 MiB.  LBMX_TILE_ORDER=0/1 overrides.
-    c->memorder = (unsigned long long)c->qs * c->elt > (96ULL << 20);
+    // memory order.  The row-major order measured faster only for streaming
+    // rows with planes of up to 64 MiB (512x128x256 in FP32 and 16-bit);
+    // memory order was faster for 128 MiB planes and more (FP64 at that
+    // size, every type at 1024x256x512) and for rows that are not whole
+    // cache lines (350x140x280: +7 %).  The switch is at 96 MiB.
+    // LBMX_TILE_ORDER=0/1 overrides.
+    c->memorder = !c->streaming || (unsigned long long)c->qs * c->elt > (96ULL << 20);
     if (const char *e = std::getenv("LBMX_TILE_ORDER")) c->memorder = std::atoi(e) != 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

@@ -49,7 +49,7 @@ enum : int {
     FLAG_WIDE = 512,       // the population array has 2^32 bytes or more
     FLAG_IMPULSE_X = 1024, // g_y = g_z = 0 and x-only drag: the y, z forces are 0
     FLAG_STREAMING = 2048, // rows start on cache lines: aligned accesses are non-temporal
-    FLAG_MEMORDER = 4096   // tiles numbered in memory order (planes above 96 MiB)
+    FLAG_MEMORDER = 4096   // tiles numbered in memory order (rows not streaming, or planes above 96 MiB)
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
