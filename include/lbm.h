@@ -112,7 +112,23 @@ size_t lbm_required_bytes(const lbm_params *p);
  * >= lbm_required_bytes(p), 256-byte aligned, that must outlive the context.
  * EINVAL for bad parameters (tau0 <= 0.5, a dimension < 1, periodic on one
  * end only, unknown storage); ENOMEM if the buffer is too small or the
- * allocation fails.  *out is NULL on failure. */
+ * allocation fails.  *out is NULL on failure.
+ *
+ * Launch choices are made here from the grid and storage type; environment
+ * variables read at this call override them (for tests and tuning; the
+ * populations are bit-identical under every choice, FP64 diagnostic sums
+ * may differ in their last bits through the summation order):
+ *   LBMX_BX=32|64|128|256   tile width in x (default: the widest of 256, 128,
+ *                           64 that pads a row least)
+ *   LBMX_QPAD=bytes         pad between population planes (default 1024)
+ *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1)
+ *   LBMX_WIDE=0|1           64-bit population addresses (default: only when
+ *                           buffer resources cannot address the array)
+ *   LBMX_STREAMING=0|1      non-temporal population accesses (default: when a
+ *                           row is a whole number of 128-byte lines)
+ *   LBMX_TILE_ORDER=0|1     row-major or memory-order tile numbering (default:
+ *                           memory order unless rows stream and a plane is at
+ *                           most 96 MiB) */
 lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out);
 
 /* Release the context (and its device memory if the library allocated it). */

@@ -145,7 +145,10 @@ long long plane_stride(long long n, size_t elt) {
     long long per = (long long)(kAlign / elt);
     long long qs = (n + per - 1) / per * per;
     long long pad_bytes = 1024;
-    if (const char *e = std::getenv("LBMX_QPAD")) pad_bytes = std::atoll(e);
+    if (const char *e = std::getenv("LBMX_QPAD")) {
+        const long long v = std::atoll(e);
+        if (v >= 0 && v <= (1LL << 30)) pad_bytes = v;
+    }
     qs += (long long)(align_up((size_t)pad_bytes, kAlign) / elt);
     return qs;
 }
