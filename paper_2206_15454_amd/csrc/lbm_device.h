@@ -74,13 +74,11 @@ template <class T> __device__ __forceinline__ void pop_st(T *p, T v) { *p = v; }
 // c_x != 0 are shifted by one cell: the lines at a wavefront's ends are
 // shared with the adjacent wavefront, which finds them in L2 only with the
 // default policy.  Rows that are not whole lines share their end lines with
-// the next row, which a later block reads: they keep the default policy.
+// the next row: they keep the default policy (streaming them was measured
+// slower in either tile order).
 template <bool STREAM> constexpr int policy_local() { return STREAM ? 2 : 0; }
 template <bool STREAM> constexpr int policy_neigh(int q) { return STREAM && CX[q] == 0 ? 2 : 0; }
 
-// Storage codecs: T is the element type in HBM, C the arithmetic type.
-// Stored values are shifted populations f_q - w_q.  st() takes 32 random bits
-// (used only by the stochastically rounded type).
 // Reciprocal and square root in the arithmetic type of a step.  FP32 uses
 // the hardware instructions (v_rcp_f32, v_sqrt_f32: within 1 ulp of the
 // correctly rounded result, one instruction each instead of a refinement
@@ -98,6 +96,9 @@ template <class C> __device__ __forceinline__ C arith_sqrt(C x) {
         return sqrt(x);
 }
 
+// Storage codecs: T is the element type in HBM, C the arithmetic type.
+// Stored values are shifted populations f_q - w_q.  st() takes 32 random bits
+// (used only by the stochastically rounded type).
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
     using T = double;
