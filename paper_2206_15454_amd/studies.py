@@ -494,9 +494,60 @@ def small_cases(out, repeats=5):
     return res
 
 
+def apriori_study(out, fine_steps=20000, batch=8192):
+    """What the trained closure gains over the Smagorinsky closure a priori:
+    both predict the filtered target nu_t of fresh samples (a new run of the
+    canopy case at twice the resolution, box-filtered 2x2x2) from the same
+    features.  Score: explained variance 1 - L / var(y/s) with the training
+    loss L = mean((nu_t,pred - nu_t,target)^2) / s^2.  Smagorinsky (Sec. 2.2)
+    needs only |P| = sqrt(tr P^2), P = Pi_neq / (rho c_s^2): X = 6 sqrt(2)
+    C_s |P|, nu_t = X / (6 (sqrt(tau0^2 + X) + tau0)), the form of the step."""
+    import torch
+
+    dev = torch.device("cuda")
+    wf, wc = inputs.C4, inputs.C2
+    lad_c = _lad(wc)
+    h_c = wc.lad_lalic[0]
+    rho, u = inputs.init_fields_torch(wf, dev)
+    fine = make(wf, "f32", rho, u)
+    del rho, u
+    ms = timed_steps(fine, fine_steps, torch, 2000, "fine")
+    X, y = fine.closure_samples(wc.tau0, h_c, lad_c)
+    fine.close()
+    p, mean, std, lo, hi, s, _ = closure.read_blob(closure.trained_blob())
+    ys = y.double() / s
+    var = float(ys.var())
+    # the network (its BF16 weights, the training forward pass)
+    tr = lbm.Trainer(p, mean, std, s, max_batch=batch)
+    n = (y.numel() // batch) * batch
+    tot = 0.0
+    for b in range(0, n, batch):
+        tot += tr.step(X[b:b + batch], y[b:b + batch], update=False) * batch
+    tr.close()
+    l_net = tot / n
+    # Smagorinsky from the same samples
+    tau0, cs = wc.tau0, wc.c_smag
+    xs = 6.0 * math.sqrt(2.0) * cs * X[:n, 5].double()
+    nu_s = xs / (6.0 * (torch.sqrt(tau0 * tau0 + xs) + tau0))
+    l_smag = float(((nu_s - y[:n].double()) / s).pow(2).mean())
+    Xl = X[:n].double().cpu().numpy()
+    inr = np.all((Xl >= lo) & (Xl <= hi), axis=1)
+    res = {"fine": {"cells": wf.n, "steps": fine_steps, "MLUPS": wf.n * fine_steps / ms / 1e3},
+           "samples": int(n), "target_mean": float(y.mean()), "target_variance_scaled": var,
+           "in_training_range": float(inr.mean()),
+           "network": {"loss": l_net, "explained_variance": 1.0 - l_net / var},
+           "smagorinsky": {"loss": l_smag, "explained_variance": 1.0 - l_smag / var,
+                           "mean_nu_t": float(nu_s.mean())}}
+    _log("apriori", json.dumps(res))
+    with open(os.path.join(out, "apriori_study.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small", "layer"])
+    ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small", "layer",
+                                      "apriori"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
@@ -524,6 +575,8 @@ def main():
     elif args.study == "layer":
         layer_study(args.out, coarse_steps=args.coarse_steps,
                     avg_from=args.avg_from or args.coarse_steps // 2)
+    elif args.study == "apriori":
+        apriori_study(args.out, fine_steps=args.fine_steps // 2)
     else:
         abl_study(args.out, steps=args.long_steps, avg_from=args.avg_from or args.long_steps // 2)
 
