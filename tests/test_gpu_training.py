@@ -121,3 +121,46 @@ def test_closure_samples_match_oracle():
         ec = float(np.max(np.abs(Xg[:, c] - Xo[:, c])) / scale[c])
         print(f"feature {c}: error / scale {ec:.3e}")
         assert ec <= 2e-3, c
+
+
+def test_trained_closure_beats_smagorinsky_a_priori():
+    """What the trained network gains over the method without it, a priori:
+    filtered samples of a fresh run at twice the resolution (the canopy
+    case's physics on 256x128x128, so 128x64x64 coarse samples after 20 000
+    fine steps) are predicted by the committed network and by the Smagorinsky
+    closure of the coarse case (Sec. 2.2, in the form of the step, from the
+    same feature |P|).  The network's loss must be a small fraction of the
+    Smagorinsky loss; on 16.8 M samples of the full-size case the ratio is
+    0.008."""
+    import math
+
+    import torch
+
+    from paper_2206_15454_amd import lbm, studies
+
+    wf = inputs.scaled(inputs.C4, 256, 128, 128)
+    wc = inputs.scaled(inputs.C2, 128, 64, 64)
+    rho, u = inputs.init_fields_torch(wf, torch.device("cuda"))
+    fine = studies.make(wf, "f32", rho, u)
+    fine.step(20000)
+    X, y = fine.closure_samples(wc.tau0, wc.lad_lalic[0], studies._lad(wc))
+    d = fine.diag()
+    fine.close()
+    assert d["nonfinite"] == 0
+    p, mean, std, lo, hi, s, _ = closure.read_blob(closure.trained_blob())
+    batch = 8192
+    n = (y.numel() // batch) * batch
+    var = float((y[:n].double() / s).var())
+    assert var > 1e-3, var  # the flow has subfilter stress to predict
+    tr = lbm.Trainer(p, mean, std, s, max_batch=batch)
+    l_net = sum(tr.step(X[b:b + batch], y[b:b + batch], update=False)
+                for b in range(0, n, batch)) * batch / n
+    tr.close()
+    xs = 6.0 * math.sqrt(2.0) * wc.c_smag * X[:n, 5].double()
+    nu_s = xs / (6.0 * (torch.sqrt(wc.tau0 * wc.tau0 + xs) + wc.tau0))
+    l_smag = float(((nu_s - y[:n].double()) / s).pow(2).mean())
+    print(f"a priori on {n} samples: target variance {var:.3f}, network loss {l_net:.4f} "
+          f"(explained {1 - l_net / var:.3f}), Smagorinsky loss {l_smag:.4f} "
+          f"(explained {1 - l_smag / var:.3f})")
+    assert l_net < 0.25 * l_smag
+    assert 1.0 - l_net / var > 0.5
