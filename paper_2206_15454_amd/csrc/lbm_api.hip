@@ -494,6 +494,9 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         const bool evaluate = learned && c->closure_lag == 0;
         if (evaluate) {
             a.flags |= FLAG_MLP;
+            // the learned-closure kernel addresses the array through the two
+            // array resources for every type (FP32 included)
+            if (!pop_array_fits((unsigned long long)c->qs * c->elt)) a.flags |= FLAG_WIDE;
             if (c->closure_every > 1) a.flags |= FLAG_NUT_OUT;
             a.fb_slot = (int)(c->evals & 1);
         } else if (learned) {

@@ -233,8 +233,11 @@ template <class Base> struct PopBuf : Base {
 constexpr bool pop_planes(int st) { return st == ST_F32; }
 template <int ST>
 using PopBufOf = PopBuf<std::conditional_t<pop_planes(ST), PopPlanes<ST>, PopArray<ST>>>;
+constexpr bool pop_array_fits(unsigned long long plane_bytes) {
+    return plane_bytes * kArraySplit < (1ULL << 32);
+}
 constexpr bool pop_wide(int st, unsigned long long plane_bytes) {
-    return (pop_planes(st) ? plane_bytes : plane_bytes * kArraySplit) >= (1ULL << 32);
+    return pop_planes(st) ? plane_bytes >= (1ULL << 32) : !pop_array_fits(plane_bytes);
 }
 
 template <int ST> struct PopGlobal {

@@ -75,11 +75,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     using T = typename CD::T;
     using C = typename CD::C;
     // population array: buffer resources, or 64-bit addresses for arrays
-    // too large for them (the learned-closure kernel in FP32 keeps 64-bit
-    // addresses: 19 per-plane resources would take the scalar registers that
-    // the network needs)
-    using Pop = std::conditional_t<(VAR & VAR_WIDE) != 0 || (LEARNED && pop_planes(ST)),
-                                   PopGlobal<ST>, PopBufOf<ST>>;
+    // too large for them.  The learned-closure kernel uses the two array
+    // resources for every type: 19 per-plane resources would take the scalar
+    // registers that the network needs.
+    using Pop = std::conditional_t<(VAR & VAR_WIDE) != 0, PopGlobal<ST>,
+                                   std::conditional_t<LEARNED, PopBuf<PopArray<ST>>, PopBufOf<ST>>>;
     Pop pop;
     pop.init(static_cast<T *>(a.f), a.qs);
     // kernel scalars in the arithmetic type (FP32 copies avoid per-thread conversions)
