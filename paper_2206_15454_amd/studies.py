@@ -548,7 +548,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small", "layer",
                                       "apriori"])
-    ap.add_argument("--out", default="gpurun_out")
+    ap.add_argument("--out", default="studies_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
     ap.add_argument("--long-steps", type=int, default=20000)
