@@ -151,8 +151,9 @@ lbm_status lbm_set_stream(lbm_ctx *ctx, void *stream);
 lbm_status lbm_set_canopy(lbm_ctx *ctx, double cd, const double *lad, int32_t ny,
                           int32_t vector_drag);
 
-/* Heterogeneous forest (Sec. 3, the forest description before Algorithm 2,
- * and Algorithm 2).  Forest code of a cell (uint32, 0 = not forest):
+/* Heterogeneous forest (Sec. 3, the forest description before Algorithm 1,
+ * alg:forestGASCANS, and that algorithm's set-up steps).  Forest code of a
+ * cell (uint32, 0 = not forest):
  *   bits  0-9   h   height of the cell's forest object in cells (1..1023),
  *                   the rows spanned by its bounding box;
  *   bits 10-19  y   row of the cell minus the object's lowest row (< h);
@@ -219,16 +220,23 @@ lbm_status lbm_set_closure_interval(lbm_ctx *ctx, int32_t every);
  * read back before the first step are rho, u and nu_t = 0.  EINVAL for NULL. */
 lbm_status lbm_init(lbm_ctx *ctx, const double *rho, const double *u, int32_t on_device);
 
-/* Enqueue n >= 0 time steps, one fused kernel launch each (stream, walls,
- * moments, canopy drag, closure, equilibrium + Guo forcing + BGK, in-place
- * store), asynchronously.  The last step of the call also writes the moments
- * (rho, u, nu_t) read by lbm_moments.  ESTATE before lbm_init or after an
- * instability was reported. */
+/* Enqueue n >= 0 time steps, one fused kernel launch each, asynchronously.
+ * One step is the time loop body of Algorithm 1 (alg:forestGASCANS): stream
+ * (Sec. 2.1, Eq. lbe; walls of Sec. 4 and Sec. 5.1), velocity (Eqs. density,
+ * momentum), forest force and corrected velocity (Sec. 2.3, Eq.
+ * forestForce), eddy viscosity (Sec. 2.2, Eqs. nu_t, strain and tau_total),
+ * and the forced BGK collision (Eqs. bgk, local_eq, bodyforce), stored in
+ * place.  The last step of the call also writes the moments (rho, u, nu_t)
+ * and the per-wavefront FP64 diagnostics read by lbm_moments.  ESTATE before
+ * lbm_init or after an instability was reported; EINVAL for n < 0. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* Synchronise the stream, then copy the moments of the latest step (FP64,
  * rho [N], u [3][N], nu_t [N]; any pointer may be NULL) and, if d != NULL,
- * the FP64 diagnostics (deterministic two-pass reductions).  EUNSTABLE (with
+ * the FP64 diagnostics (deterministic two-pass reductions).  rho and u are
+ * the density and force-corrected velocity of Sec. 2.1 (Eqs. density,
+ * momentum), nu_t the eddy viscosity of the step's closure (Sec. 2.2); the
+ * mass and momentum are their FP64 sums over the cells.  EUNSTABLE (with
  * the outputs still written) if a non-finite value or max |u| > 0.35 is
  * found; later steps then return ESTATE until lbm_init or lbm_set_f. */
 lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *u, double *nu_t, int32_t on_device,
@@ -243,7 +251,11 @@ lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *u, double *nu_t, int32
 lbm_status lbm_stats(lbm_ctx *ctx, int32_t op, int32_t every, double *prof, int64_t *nsamples);
 
 /* Overwrite the state with post-collision populations f [19][N] (FP64,
- * rounded into the storage type); t is unchanged.  Clears an instability. */
+ * rounded into the storage type), stored in the slots the next step reads
+ * (the in-place buffer's layout alternates between steps; t and that
+ * alternation are unchanged, so a state saved with lbm_get_f and restored
+ * continues bit for bit).  Clears an instability.  The moments read by
+ * lbm_moments stay those of the latest step. */
 lbm_status lbm_set_f(lbm_ctx *ctx, const double *f, int32_t on_device);
 
 /* Read the current post-collision populations (decoded to FP64) [19][N];

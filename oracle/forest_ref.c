@@ -6,7 +6,7 @@
  * library, which has its own implementation of the same interface.
  *
  * Method (Shao et al., arXiv 2206.15454, Sec. 3, the forest description
- * before Algorithm 2, and Algorithm 2): every cell that holds at least one
+ * before Algorithm 1, and the set-up steps of Algorithm 1): every cell that holds at least one
  * point of the forest point cloud is a forest cell.  Its code stores the
  * height h of the forest object it belongs to (vertical extent of the
  * object's bounding box), its own height y above the object's lowest cell

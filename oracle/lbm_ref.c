@@ -294,7 +294,7 @@ int ref_set_canopy(void *h, double cd, const double *lad, int ny, int vector_dra
 
 double ref_forest_lad(uint32_t code, double afm, int constant);
 
-/* Heterogeneous forest (Sec. 3, Algorithm 2): the LAD of every cell from
+/* Heterogeneous forest (Sec. 3, Algorithm 1): the LAD of every cell from
  * its forest code (forest_ref.c); replaces the per-row profile until the
  * next ref_set_canopy. */
 int ref_set_forest(void *h, double cd, double afm, int constant, const uint32_t *codes,

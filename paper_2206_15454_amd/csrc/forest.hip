@@ -1,5 +1,5 @@
 // Heterogeneous forest, host side (Sec. 3, the forest description before
-// Algorithm 2, and Algorithm 2): point cloud -> per-cell forest codes, and
+// Algorithm 1, and the set-up steps of Algorithm 1): point cloud -> per-cell forest codes, and
 // codes -> the compact form the step kernel reads (a 16-bit index per cell
 // into a table of distinct LAD values).
 //

@@ -46,8 +46,9 @@ struct lbm_ctx {
     float *ftabf = nullptr;    // the same in FP32
     bool forest = false;       // lbm_set_forest active
     double *imp = nullptr;
+    double *dg = nullptr;    // per-wavefront diagnostics of the last moments step
     double *stats = nullptr;
-    double *red = nullptr;   // diag partials [kRedBlocks*6] + final [16]
+    double *red = nullptr;   // diag partials [kDiagRedDoubles] + final [16]
     double *prof = nullptr;  // [ny*10]
     void *mlp = nullptr;     // learned closure parameters
     // host state
@@ -64,6 +65,8 @@ struct lbm_ctx {
     int closure_lag = 0;     // steps since its last evaluation (0: evaluate next)
     int64_t evals = 0;       // evaluations so far (fallback counter slot = evals & 1)
     int last_fb_slot = 0;    // slot of the last evaluation
+    int mlp_grid[4] = {0, 0, 0, 0};  // persistent grid of the learned-closure kernel per variant
+    bool diag_fresh = false; // dg holds the diagnostics of the moments lbm_moments reads
     std::string err;
 };
 
@@ -74,7 +77,6 @@ bool forest_table(const uint32_t *codes, long long n, double afm, bool constant,
 
 namespace {
 
-constexpr int kRedBlocks = 1024;
 constexpr size_t kAlign = 256;
 const char *kNoCtx = "lbm: NULL context";
 
@@ -154,7 +156,7 @@ long long plane_stride(long long n, size_t elt) {
 }
 
 struct Layout {
-    size_t f, mom, lad, imp, stats, red, prof, mlp, fidx, ftab, ftabf, total;
+    size_t f, mom, lad, imp, dg, stats, red, prof, mlp, fidx, ftab, ftabf, total;
 };
 
 Layout layout(const lbm_params *p) {
@@ -176,8 +178,9 @@ Layout layout(const lbm_params *p) {
     L.mom = take((size_t)5 * n * celt);
     L.lad = take((size_t)p->ny * 8);
     L.imp = take((size_t)ntiles * 4 * 3 * 8);  // one triple per wavefront of a tile
+    L.dg = take((size_t)ntiles * 4 * 6 * 8);   // one diagnostics record per wavefront
     L.stats = take((size_t)p->ny * nbx * nbz * 10 * 8);
-    L.red = take((size_t)(kRedBlocks * 6 + 16) * 8);
+    L.red = take((size_t)(kDiagRedDoubles + 16) * 8);
     L.prof = take((size_t)p->ny * 10 * 8);
     L.mlp = take(kMlpDeviceBytes);
     L.fidx = take(p->forest_map ? (size_t)n * 2 : 0);
@@ -288,6 +291,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->mom = b + L.mom;
     c->lad = reinterpret_cast<double *>(b + L.lad);
     c->imp = reinterpret_cast<double *>(b + L.imp);
+    c->dg = reinterpret_cast<double *>(b + L.dg);
     c->stats = reinterpret_cast<double *>(b + L.stats);
     c->red = reinterpret_cast<double *>(b + L.red);
     c->prof = reinterpret_cast<double *>(b + L.prof);
@@ -426,6 +430,7 @@ lbm_status lbm_init(lbm_ctx *c, const double *rho, const double *u, int32_t on_d
     c->t = 0;
     c->parity = 0;
     c->inited = true;
+    c->diag_fresh = false;
     c->closure_lag = 0;  // the next step evaluates the learned closure
     c->unstable = false;
     return LBM_OK;
@@ -468,6 +473,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.ftabf = c->ftabf;
     a.mom = c->mom;
     a.imp = c->imp;
+    a.dg = c->dg;
     a.stats = c->stats;
     a.mlp = c->mlp;
     int base_flags = FLAG_IMPULSE;
@@ -502,8 +508,18 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         } else if (learned) {
             a.flags |= FLAG_NUT_IN;
         }
-        hipError_t e = evaluate ? launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->stream)
-                                : launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
+        hipError_t e = hipSuccess;
+        if (evaluate) {
+            // the persistent grid depends on the kernel variant only: the
+            // occupancy query runs once per variant and context
+            const int v = ((a.flags & FLAG_FOREST) ? 1 : 0) | ((a.flags & FLAG_WIDE) ? 2 : 0);
+            if (c->mlp_grid[v] == 0)
+                e = mlp_launch_grid(c->p.storage, a.flags, c->ntiles, &c->mlp_grid[v]);
+            if (e == hipSuccess)
+                e = launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->mlp_grid[v], c->stream);
+        } else {
+            e = launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
+        }
         if (e != hipSuccess) return hip_fail(c, e, "lbm_step: launch");
         if (evaluate) {
             c->last_fb_slot = a.fb_slot;
@@ -514,6 +530,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         c->t += 1;
         if (sample) c->stats_n += 1;
     }
+    if (nsteps > 0) c->diag_fresh = true;
     return LBM_OK;
 }
 
@@ -547,11 +564,14 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, double *nut, int32_t 
             }
         }
     }
+    // FP64 diagnostics: from the per-wavefront records of the last step, or
+    // from the moment planes when no step ran since lbm_init / lbm_set_f
     double out[9] = {0};
-    HIPCHK(c, launch_diag(c->p.storage, c->mom, (int)n, c->imp, 4 * c->ntiles, c->red, kRedBlocks,
-                          c->red + kRedBlocks * 6, c->stream), "lbm_moments: reduce");
-    HIPCHK(c, hipMemcpyAsync(out, c->red + kRedBlocks * 6, sizeof(out), hipMemcpyDeviceToHost,
-                             c->stream), "lbm_moments: copy diag");
+    double *dout = c->red + kDiagRedDoubles;
+    HIPCHK(c, launch_diag(c->p.storage, c->mom, (int)n, c->diag_fresh ? c->dg : nullptr, c->imp,
+                          4 * c->ntiles, c->red, dout, c->stream), "lbm_moments: reduce");
+    HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(out), hipMemcpyDeviceToHost, c->stream),
+           "lbm_moments: copy diag");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_moments: sync");
     int64_t fb = 0;
     if (c->closure == LBM_CLOSURE_MLP) {
@@ -616,11 +636,14 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *fin, int32_t on_device) {
                "lbm_set_f: copy");
         src = tmp;
     }
-    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, (int)n, c->stream), "lbm_set_f: kernel");
+    // stored where the next step reads it: the AA parity of the context
+    // continues (before the first step after lbm_init it is 0)
+    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, c->p.nx, c->p.ny, c->p.nz, c->parity,
+                           c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_set_f: kernel");
     if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_set_f: free staging");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_f: sync");
-    c->parity = 0;
     c->inited = true;
+    c->diag_fresh = false;
     c->closure_lag = 0;  // the next step evaluates the learned closure
     c->unstable = false;
     return LBM_OK;

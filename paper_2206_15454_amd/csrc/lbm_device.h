@@ -266,7 +266,9 @@ template <int ST> struct PopGlobal {
     }
 };
 
-// 32-bit integer hash (xorshift-multiply finaliser) for the rounding bits
+// 32-bit integer hash for the rounding bits: the xorshift-multiply finaliser
+// with the shifts and multipliers of C. Wellons' "lowbias32" (published
+// 2018 with his hash-prospector search, public domain)
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352dU;
@@ -311,6 +313,7 @@ struct StepArgs {
     const float *ftabf;    // the same in FP32 (FP32 arithmetic)
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
     double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront)
+    double *dg;       // [ntiles][4][6] diagnostics of the last FLAG_MOMENTS step (per wavefront)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators
     const void *mlp;  // learned closure parameters on the device
 };
@@ -351,14 +354,21 @@ __device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t m, int s) {
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s);
 hipError_t launch_init(int storage, void *f, long long qs, void *mom, const double *rho,
                        const double *u, int n, hipStream_t s);
-hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
-                        hipStream_t s);
+// populations [19][N] into the slots the next step of the given AA parity reads
+hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int ny,
+                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);
 hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
                         int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);  // EQ stores like BB
 hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
                               double *nut, int n, hipStream_t s);
-hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, int nimp,
-                       double *partial, int nblocks, double *out, hipStream_t s);
+// FP64 diagnostics into out[9] (mass, mom[3], impulse[3], max|u|, nonfinite):
+// from the per-wavefront records dg and imp (nrec each), or, with dg null,
+// mass to non-finite count from the moment planes.  red: scratch of
+// kDiagRedDoubles doubles.
+constexpr int kDiagPlaneBlocks = 1024, kDiagRecordBlocks = 512;
+constexpr int kDiagRedDoubles = kDiagPlaneBlocks * 6 + kDiagRecordBlocks * 9;
+hipError_t launch_diag(int storage, const void *mom, int n, const double *dg, const double *imp,
+                       int nrec, double *red, double *out, hipStream_t s);
 hipError_t launch_stats_read(const double *stats, int ny, int tpp, double *prof,
                              hipStream_t s);
 hipError_t launch_fill(double *p, double v, size_t n, hipStream_t s);

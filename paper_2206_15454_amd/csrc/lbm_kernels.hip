@@ -32,14 +32,22 @@ template <class C> __device__ __forceinline__ C wave_sum(C v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 // Deterministic block sum of K values (256 threads = 4 waves): wave
 // butterflies, then a fixed-order sum of the 4 wave results in FP64.
-// Thread c < K adds the block total of value c into acc[c].
+// Thread c < K adds the block total of value c into acc[c].  The barrier on
+// entry orders this call's writes of sh after the previous call's reads
+// (the persistent kernel calls it once per tile and again at its end).
 template <int K, class C>
 __device__ __forceinline__ void block_accumulate(const C (&v)[K], double *acc, double *sh) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         C s = wave_sum(v[c]);
@@ -374,8 +382,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
 
     // ---- a7: store in place --------------------------------------------------
     // random bits for stochastic rounding (unused by the other storage types):
-    // one hash of (step seed, cell), then one xorshift32 step per pair of
-    // directions, whose low and high 16 bits serve the two directions
+    // one hash of (step seed, cell), then one step of Marsaglia's xorshift32
+    // generator (shifts 13, 17, 5; "Xorshift RNGs", J. Stat. Softw. 8, 2003)
+    // per pair of directions, whose low and high 16 bits serve the two
+    // directions
     uint32_t rstate = (ST == ST_BF16SR) ? mix32(a.seed ^ ((uint32_t)self * 0x9E3779B1u)) | 1u : 0u;
     uint32_t rpair = 0;
     auto rnd = [&](int q) -> uint32_t {
@@ -441,6 +451,33 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             m[3 * ncell + self] = uz;
         }
         m[4 * ncell + self] = nut;
+    }
+
+    // ---- a9: FP64 diagnostics of this collision, one record per wavefront --
+    // (mass, momentum, max |u|, non-finite cells of the moments written
+    // above); lbm_moments reduces the records instead of reading the moment
+    // planes again.  A non-finite cell adds nothing to the sums.
+    if (a.flags & FLAG_MOMENTS) {
+        const bool fin = active && __builtin_isfinite(rho) && __builtin_isfinite(ux) &&
+                         __builtin_isfinite(uy) && __builtin_isfinite(uz) &&
+                         __builtin_isfinite(nut);
+        const double r = fin ? (double)rho : 0.0;
+        const double dux = fin ? (double)ux : 0.0, duy = fin ? (double)uy : 0.0,
+                     duz = fin ? (double)uz : 0.0;
+        const double m0 = wave_sum(r), m1 = wave_sum(r * dux), m2 = wave_sum(r * duy),
+                     m3 = wave_sum(r * duz);
+        const double umax = wave_max(sqrt(dux * dux + duy * duy + duz * duz));
+        const unsigned long long bad = __builtin_amdgcn_ballot_w64(active && !fin);
+        const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+        if ((tid & 63) == 0) {
+            double *rec = a.dg + 6 * (4 * (long long)tile + (tid >> 6));
+            rec[0] = m0;
+            rec[1] = m1;
+            rec[2] = m2;
+            rec[3] = m3;
+            rec[4] = umax;
+            rec[5] = (double)__builtin_popcountll(bad);
+        }
     }
 
     // ---- body-force impulse and plane statistics (FP64 accumulators) ------
@@ -521,10 +558,8 @@ void lbm_step_mlp_kernel(const StepArgs a) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
     if ((tid & 63) == 0 && fsum) atomicAdd(&P->fallback[a.fb_slot], (unsigned long long)fsum);
-    if (a.flags & FLAG_IMPULSE) {
-        __syncthreads();  // sh may still be read by the last tile's statistics
+    if (a.flags & FLAG_IMPULSE)
         block_accumulate<3>(imp, a.imp + 3 * (long long)blockIdx.x, sh);  // grid <= ntiles
-    }
 }
 
 // f = feq(rho, u) as post-collision populations, stored shifted in the
@@ -555,18 +590,44 @@ __global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, void 
     m[4 * (long long)n + x] = (C)0;
 }
 
+// Slot of the in-place buffer that holds the post-collision population
+// f*_q(x) before a step of the given AA parity: after a local step (parity 0
+// next) slot opp(q) of x; after a neighbour step (parity 1 next) where the
+// neighbour step wrote it (slot q of x + c_q, or the wall's slot).  A
+// bijection of the 19 N slots (every cell reads and writes the same 19).
+__device__ __forceinline__ long long slot_of(int q, long long x, int i, int j, int k, int nx,
+                                             int ny, int nz, int parity, int bc_lo, int bc_hi,
+                                             long long qs) {
+    if (parity == 0) return opp(q) * qs + x;
+    const int cx = CX[q], cy = CY[q], cz = CZ[q];
+    const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
+    const int jt = j + cy;
+    if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
+        if ((jt < 0 ? bc_lo : bc_hi) != BC_FREESLIP)  // bounce-back or forced equilibrium
+            return opp(q) * qs + x;
+        return mir(q) * qs + ((long long)kt * ny + j) * nx + it;
+    }
+    return q * qs + ((long long)kt * ny + (jt + ny) % ny) * nx + it;
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, const double *fin,
-                                                    int n) {
+                                                    int nx, int ny, int nz, int parity, int bc_lo,
+                                                    int bc_hi) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)nx * ny * nz;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     T *f = static_cast<T *>(fp);
+    const int i = (int)(x % nx);
+    const int j = (int)((x / nx) % ny);
+    const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        CD::st(f + opp(q) * qs + x, (C)(fin[(long long)q * n + x] - weight(q)));
+        const long long at = slot_of(q, x, i, j, k, nx, ny, nz, parity, bc_lo, bc_hi, qs);
+        CD::st(f + at, (C)(fin[(long long)q * n + x] - weight(q)));
     });
 }
 
@@ -588,29 +649,8 @@ __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs
     const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        constexpr int cx = CX[q], cy = CY[q], cz = CZ[q];
-        long long src;
-        int slot;
-        if (parity == 0) {
-            slot = opp(q);
-            src = x;
-        } else {
-            const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
-            const int jt = j + cy;
-            if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
-                if ((jt < 0 ? bc_lo : bc_hi) != BC_FREESLIP) {  // bounce-back or equilibrium
-                    slot = opp(q);
-                    src = x;
-                } else {
-                    slot = mir(q);
-                    src = ((long long)kt * ny + j) * nx + it;
-                }
-            } else {
-                slot = q;
-                src = ((long long)kt * ny + (jt + ny) % ny) * nx + it;
-            }
-        }
-        fout[q * n + x] = (double)CD::ld(f + slot * qs + src) + weight(q);
+        const long long at = slot_of(q, x, i, j, k, nx, ny, nz, parity, bc_lo, bc_hi, qs);
+        fout[q * n + x] = (double)CD::ld(f + at) + weight(q);
     });
 }
 
@@ -672,32 +712,15 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const void *mom, int 
     if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// pass 2 (one block): fixed-order sums of the partials and of the impulse
-// accumulators.  out: mass, mom[3], impulse[3], max|u|, nonfinite
-__global__ __launch_bounds__(256) void diag_final_kernel(const double *partial, int nblocks,
-                                                         const double *imp, int nimp,
-                                                         double *out) {
-    __shared__ double sh[9][256];
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        s[0] += partial[b * 6 + 0];
-        s[1] += partial[b * 6 + 1];
-        s[2] += partial[b * 6 + 2];
-        s[3] += partial[b * 6 + 3];
-        s[7] = fmax(s[7], partial[b * 6 + 4]);
-        s[8] += partial[b * 6 + 5];
-    }
-    for (int b = threadIdx.x; b < nimp; b += blockDim.x) {
-        s[4] += imp[3 * b + 0];
-        s[5] += imp[3 * b + 1];
-        s[6] += imp[3 * b + 2];
-    }
-    for (int c = 0; c < 9; ++c) sh[c][threadIdx.x] = s[c];
+// Deterministic tree sum over the 256 threads of a block: K values per
+// thread in sh[K][256]; component cmax (if >= 0) takes the maximum.
+template <int K>
+__device__ __forceinline__ void block_tree(double (*sh)[256], int cmax) {
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            for (int c = 0; c < 9; ++c) {
-                if (c == 7)
+            for (int c = 0; c < K; ++c) {
+                if (c == cmax)
                     sh[c][threadIdx.x] = fmax(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
                 else
                     sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
@@ -705,6 +728,68 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double *partial, 
         }
         __syncthreads();
     }
+}
+
+// Per-wavefront records, pass 1: block b reduces records [b*chunk,
+// (b+1)*chunk) of dg ([n][6]: mass, momentum (3), max |u|, non-finite; may
+// be null) and imp ([n][3]: impulse) in FP64 into partial[b][9] = mass,
+// momentum (3), impulse (3), max |u|, non-finite.
+__global__ __launch_bounds__(256) void diag_records_kernel(const double *dg, const double *imp,
+                                                           int n, int chunk, double *partial) {
+    __shared__ double sh[9][256];
+    const int beg = blockIdx.x * chunk;
+    const int end = min(n, beg + chunk);
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = beg + (int)threadIdx.x; x < end; x += blockDim.x) {
+        if (dg) {
+            const double *d = dg + 6 * (long long)x;
+            s[0] += d[0];
+            s[1] += d[1];
+            s[2] += d[2];
+            s[3] += d[3];
+            s[7] = fmax(s[7], d[4]);
+            s[8] += d[5];
+        }
+        const double *m = imp + 3 * (long long)x;
+        s[4] += m[0];
+        s[5] += m[1];
+        s[6] += m[2];
+    }
+    for (int c = 0; c < 9; ++c) sh[c][threadIdx.x] = s[c];
+    block_tree<9>(sh, 7);
+    if (threadIdx.x < 9) partial[blockIdx.x * 9 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// pass 2 (one block): fixed-order sums of the nb records of pass 1 and, when
+// the mass, momentum, max |u| and non-finite count come from the moment
+// planes instead (pm != null: diag_partial_kernel's nm records of 6), of
+// those.  out: mass, mom[3], impulse[3], max|u|, nonfinite
+__global__ __launch_bounds__(256) void diag_final_kernel(const double *ps, int nb,
+                                                         const double *pm, int nm,
+                                                         double *out) {
+    __shared__ double sh[9][256];
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        for (int c = 0; c < 9; ++c) {
+            if (c == 7)
+                s[c] = fmax(s[c], ps[b * 9 + c]);
+            else
+                s[c] += ps[b * 9 + c];
+        }
+    }
+    if (pm) {
+        s[0] = s[1] = s[2] = s[3] = s[7] = s[8] = 0.0;
+        for (int b = threadIdx.x; b < nm; b += blockDim.x) {
+            s[0] += pm[b * 6 + 0];
+            s[1] += pm[b * 6 + 1];
+            s[2] += pm[b * 6 + 2];
+            s[3] += pm[b * 6 + 3];
+            s[7] = fmax(s[7], pm[b * 6 + 4]);
+            s[8] += pm[b * 6 + 5];
+        }
+    }
+    for (int c = 0; c < 9; ++c) sh[c][threadIdx.x] = s[c];
+    block_tree<9>(sh, 7);
     if (threadIdx.x < 9) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
@@ -798,20 +883,27 @@ hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
-    if (bx * bz != 256 || a.ntiles < 1 || a.mlp == nullptr) return hipErrorInvalidValue;
+hipError_t mlp_launch_grid(int storage, int flags, int ntiles, int *grid) {
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    if (a.flags & FLAG_NUT_IN) return hipErrorInvalidValue;  // the network computes nu_t
-    LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(a.flags, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+    LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(flags, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                                &per_cu, reinterpret_cast<const void *>(lbm_step_mlp_kernel<S, V>),
                                256, 0)));
     if (e != hipSuccess) return e;
-    int grid = (per_cu > 0 ? per_cu : 1) * ncu;
-    grid = grid >= 8 ? grid / 8 * 8 : grid;
-    if (grid > a.ntiles) grid = a.ntiles;
+    int g = (per_cu > 0 ? per_cu : 1) * ncu;
+    g = g >= 8 ? g / 8 * 8 : g;
+    if (g > ntiles) g = ntiles;
+    *grid = g > 0 ? g : 1;
+    return hipSuccess;
+}
+
+hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, int grid,
+                           hipStream_t s) {
+    if (bx * bz != 256 || a.ntiles < 1 || a.mlp == nullptr || grid < 1 || grid > a.ntiles)
+        return hipErrorInvalidValue;
+    if (a.flags & FLAG_NUT_IN) return hipErrorInvalidValue;  // the network computes nu_t
     LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(a.flags, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, V>),
                                                                         dim3(grid), dim3(bx, bz),
                                                                         0, s, a)));
@@ -825,10 +917,11 @@ hipError_t launch_init(int storage, void *f, long long qs, void *mom, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int n,
-                        hipStream_t s) {
+hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int ny,
+                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, fin, n));
+                                              s, f, qs, fin, nx, ny, nz, parity, bc_lo, bc_hi));
     return hipGetLastError();
 }
 
@@ -847,15 +940,31 @@ hipError_t launch_moments_out(int storage, const void *mom, double *rho, double 
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int storage, const void *mom, int n, const double *imp, int nimp,
-                       double *partial, int nblocks, double *out, hipStream_t s) {
-    const int chunk = (n + nblocks - 1) / nblocks;
-    const int nb = (n + chunk - 1) / chunk;
-    LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(diag_partial_kernel<S>, dim3(nb), dim3(256), 0, s,
-                                              mom, n, chunk, partial));
+hipError_t launch_diag(int storage, const void *mom, int n, const double *dg, const double *imp,
+                       int nrec, double *red, double *out, hipStream_t s) {
+    double *pm = nullptr;
+    int nm = 0;
+    if (!dg) {
+        // the moment planes (after lbm_init): one pass over N cells
+        const int chunk = (n + kDiagPlaneBlocks - 1) / kDiagPlaneBlocks;
+        nm = (n + chunk - 1) / chunk;
+        pm = red;
+        LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(diag_partial_kernel<S>, dim3(nm), dim3(256),
+                                                  0, s, mom, n, chunk, pm));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    double *ps = red + kDiagPlaneBlocks * 6;
+    int nb = (nrec + 255) / 256;
+    if (nb > kDiagRecordBlocks) nb = kDiagRecordBlocks;
+    if (nb < 1) nb = 1;
+    const int chunk = (nrec + nb - 1) / nb;
+    nb = chunk > 0 ? (nrec + chunk - 1) / chunk : 1;
+    hipLaunchKernelGGL(diag_records_kernel, dim3(nb), dim3(256), 0, s, dg, imp, nrec,
+                       chunk > 0 ? chunk : 1, ps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partial, nb, imp, nimp, out);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, ps, nb, pm, nm, out);
     return hipGetLastError();
 }
 

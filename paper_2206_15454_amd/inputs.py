@@ -128,7 +128,7 @@ CHANNEL = Workload(name="paper-channel-372x62x124", nx=372, ny=62, nz=124, stora
                    bc_hi=BC_BOUNCEBACK, cd=0.0, u_ref=0.03, y_ref=31.0, noise=0.05, seed=6,
                    steps=20000, channel=True)
 
-# A heterogeneous forest (Sec. 3 forest codes, Algorithm 2) on the production
+# A heterogeneous forest (Sec. 3 forest codes, Algorithm 1) on the production
 # grid: about 1640 trees of 8-16 cells, crowns that overlap into patches,
 # a_fm = 0.36 per cell (the peak of the LAI-2 profile above), y_m = 0.7 h.
 FOREST = replace(C2, name="forest-patches-512x128x256-f32", lad_lalic=None,

@@ -13,7 +13,7 @@ import pytest
 
 from oracle import ref
 from paper_2206_15454_amd import closure, inputs
-from tests.gpu_common import make_pair, normwise, require_gpu
+from tests.gpu_common import make_pair, normwise, require_gpu, round_storage, ulp
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,7 @@ def blob_with_range(lo, hi, seed=1, scale=1e-4, h=10.0):
     return closure.make_blob(random_params(seed), MEAN, STD, lo, hi, scale, h)
 
 
+_, W_ = ref.lattice()
 WIDE_LO = np.full(9, -1e30)
 WIDE_HI = np.full(9, 1e30)
 
@@ -193,3 +194,120 @@ def test_closure_interval_with_a_constant_network_is_exact(storage):
 
     with pytest.raises(lbm.LBMError):
         sims[2].set_closure_interval(0)
+
+
+# the 200-step bounds of the Smagorinsky step per storage type (the
+# low-precision parity tests): the learned runs below stay within them
+STEP_BOUNDS = {"f32": {"rho": 1e-6, "u": 2e-5}, "f16s": {"rho": 1e-4, "u": 2e-3},
+               "bf16s": {"rho": 1e-3, "u": 2e-2}, "bf16sr": {"rho": 1e-3, "u": 2e-2}}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s", "bf16sr"])
+def test_learned_closure_each_storage_matches_oracle(storage):
+    """The learned-closure kernel in every reduced-precision storage type,
+    at the 512-wide launch shape (256-wide tiles, streaming rows), against
+    the oracle.  The stored state S is physical: the oracle's own state
+    after 3 steps from the seeded start, rounded into the storage type (so
+    that the network's standardised inputs lie where it was set up).  From
+    S, one step in each AA parity; then ten steps.
+
+    Bounds (one step): rho and u as the plain step from a stored state (both
+    sides decode the same S; the GPU adds FP32 arithmetic); nu_t within 3e-2
+    of its largest value where the network runs (the FP64-storage bound;
+    measured there 3.3e-3) and at FP32 Smagorinsky precision (1e-3) in the
+    rows that fall back; the populations within 1 ulp of the storage type
+    plus 8 FP32 ulps of their direction's largest value plus the effect of
+    the nu_t bound on the relaxation, |f - f_eq| * 3 dnu / tau^2 with
+    |f - f_eq| <= 2 max|f~|."""
+    W4 = W_[:, None, None, None]
+    w = inputs.scaled(inputs.C1, 512, 12, 8, canopy_rows=5)
+    o, g = make_pair(w, storage=storage, seed=6)
+    o.step(3)
+    shifted = round_storage(o.get_f() - W4, storage)
+    S = shifted + W4
+    hi = WIDE_HI.copy()
+    hi[7] = 0.15  # LAD above 0.15: the canopy rows fall back to Smagorinsky
+    blob = blob_with_range(WIDE_LO.copy(), hi, seed=3)
+    o.set_closure(ref.MLP(blob))
+    g.set_closure(blob)
+    canopy = np.zeros(w.shape, dtype=bool)
+    canopy[:, :5, :] = True
+    for parity in (0, 1):
+        o.set_f(S)
+        g.set_f(S)
+        o.step(1)
+        g.step(1)
+        ro, uo, no, do = o.moments()
+        rg, ug, ng, dg = g.moments()
+        assert do["mlp_fallback"] == dg["mlp_fallback"] == canopy.sum()
+        e = {"rho": normwise(rg, ro), "u": normwise(ug, uo),
+             "nut_fallback": normwise(ng[canopy], no[canopy]),
+             "nut_learned": normwise(ng[~canopy], no[~canopy])}
+        print(storage, "parity", parity, e, "max nu_t", no.max())
+        assert e["rho"] <= 1e-6 and e["u"] <= 1e-5
+        assert e["nut_fallback"] <= 1e-3
+        assert e["nut_learned"] <= 3e-2
+        so = o.get_f() - W4
+        sg = g.get_f() - W4
+        dnu = 3e-2 * np.max(np.abs(no))
+        relax = 2 * np.max(np.abs(shifted)) * 3 * dnu / w.tau0 ** 2
+        scale = np.max(np.abs(so), axis=(1, 2, 3), keepdims=True)
+        bound = ulp(so, storage) + 8 * 2.0 ** -24 * scale + relax
+        worst = float(np.max(np.abs(sg - so) / bound))
+        print(storage, "parity", parity, "populations: max err/bound", worst)
+        assert worst <= 1.0
+        np.testing.assert_array_equal(round_storage(sg, storage), sg)
+    # Ten steps from S (the GPU continues from its own rounded states).  The
+    # nu_t error then holds the storage rounding of ten steps, which the
+    # Smagorinsky closure sees as well: a control pair (GPU Smagorinsky
+    # kernel and oracle, same S, same storage) measures it.  Smagorinsky's
+    # nu_t is linear in |Pi_neq| at these small X, the network's features
+    # reach cubic invariants of Pi_neq, so its relative sensitivity to the
+    # same Pi_neq noise is at most 3 times larger; on top comes the
+    # network's own 10-step bound in FP64 storage (5e-2).
+    oc, gc = make_pair(w, storage=storage, init=False)
+    oc.set_f(S)
+    gc.set_f(S)
+    oc.step(10)
+    gc.step(10)
+    _, _, nco, _ = oc.moments()
+    _, _, ncg, _ = gc.moments()
+    e_smag = normwise(ncg, nco)
+    o.set_f(S)
+    g.set_f(S)
+    o.step(10)
+    g.step(10)
+    ro, uo, no, do = o.moments()
+    rg, ug, ng, dg = g.moments()
+    e = {"rho": normwise(rg, ro), "u": normwise(ug, uo), "nut": normwise(ng, no)}
+    print(storage, "10 steps:", e, "Smagorinsky control nu_t:", e_smag)
+    assert do["mlp_fallback"] == dg["mlp_fallback"]
+    assert e["rho"] <= STEP_BOUNDS[storage]["rho"]
+    assert e["u"] <= max(STEP_BOUNDS[storage]["u"], 1e-5)
+    assert e["nut"] <= 3 * e_smag + 5e-2
+
+
+def test_learned_kernel_statistics_equal_plain_when_every_cell_falls_back():
+    """The persistent learned-closure kernel accumulates the plane
+    statistics through the block's shared staging area once per tile; with
+    more tiles than blocks (512x64x32: 4096 tiles), and every cell falling
+    back to Smagorinsky, its statistics equal the plain kernel's: the
+    velocity columns bit for bit (identical populations, identical
+    accumulation order), the nu_t column to its FP32 last bits."""
+    w = inputs.scaled(inputs.C1, 512, 64, 32, canopy_rows=12)
+    _, a = make_pair(w, storage="f32", seed=2)
+    _, b = make_pair(w, storage="f32", seed=2)
+    lo = WIDE_LO.copy()
+    hi = WIDE_HI.copy()
+    lo[8], hi[8] = 2.0, 3.0  # the width feature is 1: every cell is out of range
+    b.set_closure(blob_with_range(lo, hi))
+    for sim in (a, b):
+        sim.stats_reset()
+        sim.stats_enable(2)
+        sim.step(8)
+    pa, na = a.stats_read()
+    pb, nb = b.stats_read()
+    assert na == nb == 4
+    np.testing.assert_array_equal(a.get_f(), b.get_f())
+    np.testing.assert_array_equal(pb[:, :9], pa[:, :9])
+    assert np.max(np.abs(pb[:, 9] - pa[:, 9]) / np.maximum(np.abs(pa[:, 9]), 1e-30)) <= 1e-6

@@ -75,18 +75,26 @@ def test_f64_boundaries_and_ragged_grids(shape, bcs):
     assert dg["mass"] == pytest.approx(do["mass"], rel=1e-13)
 
 
+@pytest.mark.parametrize("nx", [67, 512])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "bf16sr"])
-def test_one_step_from_stored_state(storage):
-    """Both AA parities: step 1 (neighbour access) and step 2 (local)."""
-    w = inputs.scaled(inputs.C1, 67, 9, 5, canopy_rows=4)
+def test_one_step_from_stored_state(storage, nx):
+    """Both AA parities: step 1 (neighbour access) and step 2 (local).
+    nx = 67: 128-wide tiles with a ragged tail, default cache policy.
+    nx = 512: the launch shape of the 512x128x256 benchmark (256-wide tiles,
+    streaming accesses on whole-line rows, row-major tile order; FP32 with
+    one buffer resource per plane)."""
+    w = inputs.scaled(inputs.C1, nx, 9, 5, canopy_rows=4)
     o, g = make_pair(w, storage=storage, init=False)
     S = inputs.random_populations(w.shape, seed=5, base=W, scale=0.02)
     shifted = round_storage(S - W[:, None, None, None], storage)
     S = shifted + W[:, None, None, None]
-    o.set_f(S)
-    g.set_f(S)
-    np.testing.assert_array_equal(g.get_f() - W[:, None, None, None], shifted)
+    # both parities start from the same stored state S: lbm_set_f stores it
+    # where the next step reads it (a neighbour step first; after one step,
+    # a local step)
     for step in (1, 2):
+        o.set_f(S)
+        g.set_f(S)
+        np.testing.assert_array_equal(g.get_f() - W[:, None, None, None], shifted)
         o.step(1)
         g.step(1)
         fo = o.get_f()
@@ -108,9 +116,6 @@ def test_one_step_from_stored_state(storage):
         assert worst <= 1.0
         # the state after the step is representable in T
         np.testing.assert_array_equal(round_storage(sg, storage), sg)
-        # then restart both from the GPU-rounded state for the next parity
-        S = fg
-        o.set_f(S)
 
 
 @pytest.mark.parametrize("storage,bounds", [
@@ -291,3 +296,82 @@ def test_stochastic_rounding_is_unbiased():
     assert np.abs(e_sr).max() <= 1.0 + 1e-3
     assert abs(e_sr.mean()) <= 0.02
     assert 0.2 <= e_sr.std() <= 0.5  # stochastic: not always the nearest neighbour
+
+
+def test_momentum_balance_periodic_f64():
+    """FP64 storage, fully periodic without canopy: the momentum gains
+    exactly M g per step (Guo forcing: the force enters half before and
+    half after the collision) and the FP64 impulse accumulator holds
+    (t + 1) M g after t steps; both to round-off."""
+    w = inputs.scaled(inputs.C1, 64, 8, 8, bc_lo=0, bc_hi=0, canopy_rows=0,
+                      g=(1e-5, -2e-6, 3e-6))
+    _, g = make_pair(w, storage="f64", seed=2)
+    g.step(1)
+    d0 = g.diag()
+    g.step(50)
+    d1 = g.diag()
+    M = d0["mass"]
+    assert d1["mass"] == pytest.approx(M, rel=1e-14)
+    for k, gk in zip(("mom_x", "mom_y", "mom_z"), w.g):
+        dm = d1[k] - d0[k]
+        print(k, "gain", dm, "expected", 50 * M * gk)
+        assert dm == pytest.approx(50 * M * gk, rel=1e-12)
+    for k, gk in zip(("imp_x", "imp_y", "imp_z"), w.g):
+        assert d1[k] == pytest.approx(51 * M * gk, rel=1e-12)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_diagnostics_after_init_and_after_steps(storage):
+    """lbm_moments reduces the moment planes after lbm_init and the step's
+    per-wavefront records after steps: both equal the oracle's diagnostics
+    (sums over the same moments), for a grid with a ragged tile tail."""
+    w = inputs.scaled(inputs.C1, 300, 7, 5, canopy_rows=3)
+    o, g = make_pair(w, storage=storage, seed=12)
+    tol = 1e-13 if storage == "f64" else 1e-6
+    for nsteps in (0, 1, 6):
+        o.step(nsteps)
+        g.step(nsteps)
+        _, uo, _, do = o.moments()
+        _, ug, _, dg = g.moments()
+        print(storage, nsteps, {k: (do[k], dg[k]) for k in ("mass", "mom_x", "max_u")})
+        assert dg["mass"] == pytest.approx(do["mass"], rel=tol)
+        umax = np.max(np.abs(uo))
+        for k in ("mom_x", "mom_y", "mom_z"):
+            assert dg[k] == pytest.approx(do[k], rel=tol * 100, abs=tol * w.n * umax)
+        assert dg["max_u"] == pytest.approx(do["max_u"], rel=tol * 10)
+        assert dg["nonfinite"] == 0
+        # the records reduce the moments the step wrote: the sums of those
+        # moments on the host agree
+        rg, ug2, _, _ = g.moments()
+        assert dg["mass"] == pytest.approx(float(np.sum(rg)), rel=1e-13)
+        assert dg["mom_x"] == pytest.approx(float(np.sum(rg * ug2[0])), rel=1e-12,
+                                            abs=1e-15 * w.n)
+
+
+def test_instability_found_from_the_step_records():
+    """After steps the diagnostics come from the step's records: a speed
+    above 0.35 and non-finite populations are both reported (EUNSTABLE) and
+    the non-finite cells are counted."""
+    from paper_2206_15454_amd import lbm
+
+    w = inputs.scaled(inputs.C1, 64, 6, 4, bc_lo=0, bc_hi=0, canopy_rows=0)
+    g = lbm.LBM(w.nx, w.ny, w.nz, "f32", w.tau0, w.c_smag, w.g, 0, 0)
+    g.init(np.ones(g.shape), np.concatenate([np.full((1,) + g.shape, 0.4),
+                                            np.zeros((2,) + g.shape)]))
+    g.step(2)
+    with pytest.raises(lbm.LBMError) as e:
+        g.moments()
+    assert e.value.status == 5
+    rho, u, nut, d = g.moments(check=False)
+    assert d["max_u"] > 0.35 and d["nonfinite"] == 0
+    # NaN in one population of 3 cells: those cells (and their downstream
+    # neighbours after streaming) are non-finite
+    f = np.tile(W[:, None, None, None], (1,) + g.shape)
+    f[1, 0, 0, :3] = np.nan
+    g.set_f(f)
+    g.step(1)
+    rho, u, nut, d = g.moments(check=False)
+    bad = ~(np.isfinite(rho) & np.isfinite(u).all(axis=0) & np.isfinite(nut))
+    assert d["nonfinite"] == int(bad.sum()) and d["nonfinite"] >= 3
+    assert np.isfinite(d["mass"])
+    assert d["mass"] == pytest.approx(float(np.sum(rho[~bad])), rel=1e-12)

@@ -1,5 +1,5 @@
 """Pins of the oracle's heterogeneous forest (point cloud -> per-cell forest
-code -> LAD, Sec. 3 forest description, Algorithm 2, Eq. (af_theory)).
+code -> LAD, Sec. 3 forest description, Algorithm 1, Eq. (af_theory)).
 
 The connected components are checked against an independent union-find
 written here; the LAD against the homogeneous profile routine (Eq. af_theory

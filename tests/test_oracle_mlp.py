@@ -148,6 +148,70 @@ def test_features_invariants():
     assert tuple(x[6:]) == (0.3, 0.2, 1.0)
 
 
+def _feature_mlp():
+    blob = _blob(np.zeros((NH1, NIN)), np.zeros(NH1), np.zeros((NH2, NH1)), np.zeros(NH2),
+                 np.zeros(NH2), 0.0, np.zeros(NIN), np.ones(NIN), -np.ones(NIN),
+                 np.ones(NIN), 1.0, 12.0)
+    return ref.MLP(blob)
+
+
+@pytest.mark.parametrize("th", [0.0, 0.4, 1.1, 2.5])
+def test_features_closed_form_from_eigenvalues(th):
+    """P = Q diag(l) Q^T with Q a rotation about e_z (which moves e_y): tr P^k
+    = sum l^k, and with (s, c) = (sin th, cos th) the second row of Q,
+    n.P.n = l1 s^2 + l2 c^2 and n.P^2.n = l1^2 s^2 + l2^2 c^2.  A wrong
+    index, a transposed factor, tr P tr P^2 for tr P^3 or (P_yy)^2 for
+    (P^2)_yy fails one of these."""
+    m = _feature_mlp()
+    lam = np.array([3.0e-3, -1.2e-3, 0.7e-3])
+    c, s = math.cos(th), math.sin(th)
+    Q = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    P = Q @ np.diag(lam) @ Q.T
+    rho = 0.97
+    x = m.features(0.5005, rho, P * (rho / 3.0), 0.25, 0.1)
+    scale = np.max(np.abs(lam))
+    assert x[0] == pytest.approx(lam.sum(), abs=1e-15 * scale)
+    assert x[1] == pytest.approx(np.sum(lam ** 2), rel=1e-13)
+    assert x[2] == pytest.approx(np.sum(lam ** 3), rel=1e-12, abs=1e-15 * scale ** 3)
+    assert x[3] == pytest.approx(lam[0] * s * s + lam[1] * c * c, abs=1e-15 * scale)
+    assert x[4] == pytest.approx(lam[0] ** 2 * s * s + lam[1] ** 2 * c * c, rel=1e-12,
+                                 abs=1e-15 * scale ** 2)
+    assert x[5] == pytest.approx(math.sqrt(np.sum(lam ** 2)), rel=1e-13)
+
+
+def test_features_newton_identity_and_column_norm():
+    """Any symmetric P: tr P^3 = e1^3 - 3 e1 e2 + 3 e3 (Newton's identity with
+    e1 = tr P, e2 = (e1^2 - tr P^2)/2, e3 = det P) and n.P^2.n = |P n|^2 =
+    P_xy^2 + P_yy^2 + P_yz^2.  Off-diagonal-only tensors (xy and yz entries)
+    and a traceless one (tr P^3 = 3 det P) are among the cases."""
+    m = _feature_mlp()
+    rng = np.random.default_rng(11)
+    cases = []
+    for _ in range(20):
+        A = rng.normal(size=(3, 3)) * 1e-3
+        cases.append(A + A.T)
+    cases.append(np.array([[0.0, 2e-3, 0.0], [2e-3, 0.0, -1e-3], [0.0, -1e-3, 0.0]]))
+    T = rng.normal(size=(3, 3)) * 1e-3
+    T = T + T.T
+    cases.append(T - np.trace(T) / 3.0 * np.eye(3))
+    for P in cases:
+        rho = 1.02
+        x = m.features(0.5005, rho, P * (rho / 3.0), 0.5, 0.0)
+        e1 = np.trace(P)
+        p2 = np.sum(P * P)
+        e2 = 0.5 * (e1 * e1 - p2)
+        e3 = np.linalg.det(P)
+        scale3 = np.max(np.abs(P)) ** 3
+        assert x[2] == pytest.approx(e1 ** 3 - 3 * e1 * e2 + 3 * e3, abs=1e-12 * scale3)
+        assert x[4] == pytest.approx(P[0, 1] ** 2 + P[1, 1] ** 2 + P[1, 2] ** 2, rel=1e-13)
+        if abs(e1) < 1e-18:
+            assert x[2] == pytest.approx(3 * e3, abs=1e-12 * scale3)
+    # the off-diagonal case: P^2 has (a^2 + b^2) at yy, its cube has zero trace
+    x = m.features(0.5005, 1.0, cases[20] / 3.0, 0.5, 0.0)
+    assert x[4] == pytest.approx(2e-3 ** 2 + 1e-3 ** 2, rel=1e-13)
+    assert abs(x[2]) <= 1e-21
+
+
 def _closure_sim(blob, every=None, seed=4):
     from paper_2206_15454_amd import inputs
 
