@@ -292,6 +292,26 @@ lbm_status lbm_lad_lalic(double h, double ym, double afm, double lai, int32_t ny
 lbm_status lbm_closure_samples(lbm_ctx *fine, double tau0_coarse, double canopy_h,
                                const double *lad_coarse, float *X, float *y, int64_t nc);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * samples as lbm_closure_samples, bit for bit, with the work area (the
+ * filtered velocity and subfilter stress, 9 FP32 per coarse cell, and the
+ * coarse LAD) taken from a fixed device array of the library instead of
+ * allocated per call.  That array holds LBM_NOALLOC_MAX_COARSE coarse cells
+ * and LBM_NOALLOC_MAX_LAD coarse rows (about 9 MiB); each device the library
+ * runs on keeps its own copy until the process ends.  The call allocates
+ * nothing and does not synchronise: it enqueues a copy of lad_coarse (host,
+ * ny/2 values, free to reuse on return) and two kernels on the context's
+ * stream; X and y are ready when that stream is.  Every call on one device
+ * shares the array, so calls that may overlap on one device (different
+ * streams, host threads) race; calls on one stream are ordered.  Nothing in
+ * the array needs clearing between calls.  Errors as lbm_closure_samples,
+ * and EINVAL when the coarse grid exceeds either limit. */
+#define LBM_NOALLOC_MAX_COARSE 262144
+#define LBM_NOALLOC_MAX_LAD 4096
+lbm_status lbm_closure_samples_noalloc(lbm_ctx *fine, double tau0_coarse, double canopy_h,
+                                       const double *lad_coarse, float *X, float *y, int64_t nc);
+
 typedef struct lbm_trainer lbm_trainer; /* opaque */
 
 typedef struct lbm_train_params {

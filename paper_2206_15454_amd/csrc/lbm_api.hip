@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -672,17 +673,75 @@ lbm_status lbm_get_f(lbm_ctx *c, double *fout, int32_t on_device) {
     return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Arguments shared by lbm_closure_samples and its allocation-free variant;
+// *ncc receives the coarse cell count.
+lbm_status closure_samples_args(lbm_ctx *c, const char *who, double tau0_coarse, double canopy_h,
+                                const double *lad_coarse, const float *X, const float *y,
+                                int64_t nc, long long *ncc) {
+    if (!c) return LBM_EINVAL;
+    if (!c->inited) return fail(c, LBM_ESTATE, std::string(who) + ": call lbm_init first");
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    if ((nx | ny | nz) & 1) return fail(c, LBM_EINVAL, std::string(who) + ": dimensions must be even");
+    if (!X || !y || !lad_coarse) return fail(c, LBM_EINVAL, std::string(who) + ": NULL pointer");
+    *ncc = (long long)(nx / 2) * (ny / 2) * (nz / 2);
+    if (nc != *ncc)
+        return fail(c, LBM_EINVAL, std::string(who) + ": nc must be (nx/2)(ny/2)(nz/2)");
+    if (!(canopy_h > 0.0) || !(tau0_coarse > 0.5))
+        return fail(c, LBM_EINVAL, std::string(who) + ": canopy_h > 0 and tau0_coarse > 0.5");
+    return LBM_OK;
+}
+
+// Work area of lbm_closure_samples_noalloc: the coarse LAD (FP64, at most
+// LBM_NOALLOC_MAX_LAD rows) followed by the filtered velocity and subfilter
+// stress (9 FP32 per coarse cell, at most LBM_NOALLOC_MAX_COARSE cells).
+// Every device the library runs on holds its own copy for the life of the
+// process.  Nothing in it needs clearing: every call writes all of the part
+// it reads.
+constexpr size_t kNoallocLadBytes = (size_t)LBM_NOALLOC_MAX_LAD * 8;
+constexpr size_t kNoallocBytes = kNoallocLadBytes + (size_t)9 * LBM_NOALLOC_MAX_COARSE * 4;
+static_assert(kNoallocLadBytes % 256 == 0, "work part 256-byte aligned");
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, taken once per device with that
+// device current (host code never passes the symbol itself to a kernel).
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        hipError_t e2 = prev != dev ? hipSetDevice(prev) : hipSuccess;
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_closure_samples(lbm_ctx *c, double tau0_coarse, double canopy_h,
                                const double *lad_coarse, float *X, float *y, int64_t nc) {
-    if (!c) return LBM_EINVAL;
-    if (!c->inited) return fail(c, LBM_ESTATE, "lbm_closure_samples: call lbm_init first");
+    long long ncc = 0;
+    const lbm_status st = closure_samples_args(c, "lbm_closure_samples", tau0_coarse, canopy_h,
+                                               lad_coarse, X, y, nc, &ncc);
+    if (st != LBM_OK) return st;
     const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
-    if ((nx | ny | nz) & 1) return fail(c, LBM_EINVAL, "lbm_closure_samples: dimensions must be even");
-    if (!X || !y || !lad_coarse) return fail(c, LBM_EINVAL, "lbm_closure_samples: NULL pointer");
-    const long long ncc = (long long)(nx / 2) * (ny / 2) * (nz / 2);
-    if (nc != ncc) return fail(c, LBM_EINVAL, "lbm_closure_samples: nc must be (nx/2)(ny/2)(nz/2)");
-    if (!(canopy_h > 0.0) || !(tau0_coarse > 0.5))
-        return fail(c, LBM_EINVAL, "lbm_closure_samples: canopy_h > 0 and tau0_coarse > 0.5");
     float *work = nullptr;
     double *lad_d = nullptr;
     HIPCHK(c, hipMallocAsync(reinterpret_cast<void **>(&work), (size_t)9 * ncc * 4, c->stream),
@@ -697,6 +756,31 @@ lbm_status lbm_closure_samples(lbm_ctx *c, double tau0_coarse, double canopy_h,
     HIPCHK(c, hipFreeAsync(work, c->stream), "lbm_closure_samples: free");
     HIPCHK(c, hipFreeAsync(lad_d, c->stream), "lbm_closure_samples: free");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_closure_samples: sync");
+    return LBM_OK;
+}
+
+lbm_status lbm_closure_samples_noalloc(lbm_ctx *c, double tau0_coarse, double canopy_h,
+                                       const double *lad_coarse, float *X, float *y, int64_t nc) {
+    long long ncc = 0;
+    const lbm_status st = closure_samples_args(c, "lbm_closure_samples_noalloc", tau0_coarse,
+                                               canopy_h, lad_coarse, X, y, nc, &ncc);
+    if (st != LBM_OK) return st;
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    if (ncc > LBM_NOALLOC_MAX_COARSE || ny / 2 > LBM_NOALLOC_MAX_LAD)
+        return fail(c, LBM_EINVAL,
+                    "lbm_closure_samples_noalloc: at most " +
+                        std::to_string(LBM_NOALLOC_MAX_COARSE) + " coarse cells and " +
+                        std::to_string(LBM_NOALLOC_MAX_LAD) + " coarse rows (got " +
+                        std::to_string(ncc) + " cells, " + std::to_string(ny / 2) + " rows)");
+    void *base = nullptr;
+    HIPCHK(c, scratch_address(c->device, &base), "lbm_closure_samples_noalloc: scratch address");
+    double *lad_d = static_cast<double *>(base);
+    float *work = reinterpret_cast<float *>(static_cast<unsigned char *>(base) + kNoallocLadBytes);
+    HIPCHK(c, hipMemcpyAsync(lad_d, lad_coarse, (size_t)(ny / 2) * 8, hipMemcpyHostToDevice, c->stream),
+           "lbm_closure_samples_noalloc: copy lad");
+    HIPCHK(c, launch_closure_samples(c->p.storage, c->mom, nx, ny, nz, work, tau0_coarse,
+                                     1.0 / canopy_h, lad_d, X, y, c->stream),
+           "lbm_closure_samples_noalloc: kernels");
     return LBM_OK;
 }
 

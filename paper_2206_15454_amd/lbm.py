@@ -54,7 +54,11 @@ EXPORTS = ("lbm_lattice", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lb
            "lbm_moments", "lbm_stats", "lbm_set_f", "lbm_get_f", "lbm_lad_lalic",
            "lbm_closure_samples", "lbm_train_create", "lbm_train_step", "lbm_train_get",
            "lbm_train_destroy", "lbm_train_last_error", "lbm_forest_codes", "lbm_set_forest",
-           "lbm_set_closure_interval")
+           "lbm_set_closure_interval", "lbm_closure_samples_noalloc")
+
+# capacity of lbm_closure_samples_noalloc's fixed work area (include/lbm.h)
+NOALLOC_MAX_COARSE = 262144
+NOALLOC_MAX_LAD = 4096
 
 _lib = None
 
@@ -99,6 +103,8 @@ def lib():
         L.lbm_lad_lalic.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
         L.lbm_closure_samples.restype = i32
         L.lbm_closure_samples.argtypes = [vp, C.c_double, C.c_double, dp, vp, vp, i64]
+        L.lbm_closure_samples_noalloc.restype = i32
+        L.lbm_closure_samples_noalloc.argtypes = [vp, C.c_double, C.c_double, dp, vp, vp, i64]
         L.lbm_train_create.restype = i32
         L.lbm_train_create.argtypes = [C.POINTER(TrainParams), C.POINTER(C.c_float), C.POINTER(vp)]
         L.lbm_train_step.restype = i32
@@ -313,19 +319,26 @@ class LBM:
         self._check(lib().lbm_get_f(self.h, p, int(device)), "lbm_get_f")
         return out
 
-    def closure_samples(self, tau0_coarse, canopy_h, lad_coarse):
+    def closure_samples(self, tau0_coarse, canopy_h, lad_coarse, out=None, noalloc=False):
         """(X [nc, 9], y [nc]) float32 torch tensors on the device: training
-        samples of the learned closure from this (fine) simulation."""
+        samples of the learned closure from this (fine) simulation.  out:
+        (X, y) device tensors to write (allocated here if None).  noalloc:
+        call lbm_closure_samples_noalloc (no device allocation, no
+        synchronisation) instead of lbm_closure_samples."""
         torch = self.torch
         nz, ny, nx = self.shape
         nc = (nx // 2) * (ny // 2) * (nz // 2)
-        X = torch.empty((nc, 9), dtype=torch.float32, device="cuda")
-        y = torch.empty(nc, dtype=torch.float32, device="cuda")
+        if out is None:
+            X = torch.empty((nc, 9), dtype=torch.float32, device="cuda")
+            y = torch.empty(nc, dtype=torch.float32, device="cuda")
+        else:
+            X, y = out
         lad = np.ascontiguousarray(lad_coarse, dtype=np.float64)
-        self._check(lib().lbm_closure_samples(self.h, float(tau0_coarse), float(canopy_h),
-                                              lad.ctypes.data_as(C.POINTER(C.c_double)),
-                                              C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
-                                              nc), "lbm_closure_samples")
+        name = "lbm_closure_samples_noalloc" if noalloc else "lbm_closure_samples"
+        self._check(getattr(lib(), name)(self.h, float(tau0_coarse), float(canopy_h),
+                                         lad.ctypes.data_as(C.POINTER(C.c_double)),
+                                         C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                                         nc), name)
         return X, y
 
 
