@@ -66,6 +66,7 @@ struct lbm_ctx {
     int closure_lag = 0;     // steps since its last evaluation (0: evaluate next)
     int64_t evals = 0;       // evaluations so far (fallback counter slot = evals & 1)
     int last_fb_slot = 0;    // slot of the last evaluation
+    MlpConst mc{};           // learned closure scalars (kernel arguments)
     int mlp_grid[4] = {0, 0, 0, 0};  // persistent grid of the learned-closure kernel per variant
     bool diag_fresh = false; // dg holds the diagnostics of the moments lbm_moments reads
     std::string err;
@@ -385,12 +386,14 @@ lbm_status lbm_set_closure(lbm_ctx *c, int32_t closure, const void *blob, size_t
     if (closure != LBM_CLOSURE_MLP) return fail(c, LBM_EINVAL, "lbm_set_closure: unknown closure");
     std::vector<unsigned char> dev(kMlpDeviceBytes);
     std::string why;
-    if (!mlp_pack_blob(blob, nbytes, dev.data(), &why))
+    MlpConst mc{};
+    if (!mlp_pack_blob(blob, nbytes, dev.data(), &mc, &why))
         return fail(c, LBM_EINVAL, "lbm_set_closure: " + why);
     HIPCHK(c, hipMemcpyAsync(c->mlp, dev.data(), dev.size(), hipMemcpyHostToDevice, c->stream),
            "lbm_set_closure: copy");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_closure: sync");
     c->closure = LBM_CLOSURE_MLP;
+    c->mc = mc;
     c->closure_lag = 0;
     c->evals = 0;
     c->last_fb_slot = 0;
@@ -477,6 +480,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.dg = c->dg;
     a.stats = c->stats;
     a.mlp = c->mlp;
+    a.mc = c->mc;
     int base_flags = FLAG_IMPULSE;
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
     if (c->p.g[1] == 0.0 && c->p.g[2] == 0.0 && !c->vector_drag) base_flags |= FLAG_IMPULSE_X;

@@ -285,6 +285,15 @@ constexpr int aux_storage(int st) { return st == ST_BF16SR ? ST_BF16S : st; }
 // entries of the per-cell forest LAD table (16-bit index; entry 0 = no forest)
 constexpr int kForestTable = 65536;
 
+// Scalars of the learned closure that every cell reads: the standardisation
+// z = x zs + zo (zs = 1/std, zo = -mean/std), the trained range [lo, hi] of
+// the raw features, 1/h, the output scale and the output bias.  Passed in the
+// step's kernel arguments; the learned-closure kernel stages them in LDS.
+struct MlpConst {
+    float zs[9], zo[9], lo[9], hi[9];
+    float inv_h, scale, b3;
+};
+
 // Arguments of one fused step launch (passed by value as kernel arguments).
 struct StepArgs {
     void *f;          // population buffer, q-plane stride qs elements
@@ -316,6 +325,7 @@ struct StepArgs {
     double *dg;       // [ntiles][4][6] diagnostics of the last FLAG_MOMENTS step (per wavefront)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators
     const void *mlp;  // learned closure parameters on the device
+    MlpConst mc;      // learned closure scalars (FLAG_MLP)
 };
 
 // compile-time loop

@@ -72,7 +72,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <int ST, bool LEARNED, int VAR>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, const MlpFrag &frag,
-                                          short *zst, double *sh, double (&imp)[3],
+                                          const MlpConst *mc, short *zst, double *sh,
+                                          double (&imp)[3],
                                           typename Codec<ST>::C *pst, unsigned &fallbacks) {
     // a * b + c is fused only inside one expression, as written: the
     // rounding then does not depend on how the compiler lays out a kernel's
@@ -299,16 +300,15 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         // Smagorinsky (above) elsewhere
         const int tid = threadIdx.x + threadIdx.y * blockDim.x;
         const int lane = tid & 63;
-        MlpParams *P = static_cast<MlpParams *>(const_cast<void *>(a.mlp));
         float x[9];
         mlp_features((float)nxx, (float)nyy, (float)nzz, (float)nxy, (float)nxz, (float)nyz,
-                     (float)rho, ((float)j + 0.5f) * P->inv_h, (float)lad, x);
+                     (float)rho, ((float)j + 0.5f) * mc->inv_h, (float)lad, x);
         bool in_range = true;
         short z[16];
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-            in_range = in_range && (x[c] >= P->lo[c]) && (x[c] <= P->hi[c]);
-            z[c] = bf16_bits((x[c] - P->mean[c]) * P->istd[c]);
+            in_range = in_range && (x[c] >= mc->lo[c]) && (x[c] <= mc->hi[c]);
+            z[c] = bf16_bits(x[c] * mc->zs[c] + mc->zo[c]);
         }
         z[9] = z[10] = bf16_bits(1.0f);
 #pragma unroll
@@ -326,7 +326,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             wave_lds_sync();  // the previous tile's reads of this wave's staging area are done
             mlp_stage_inputs(zst, lane, z);
             wave_lds_sync();
-            const float o = mlp_forward_wave(frag, zst, lane) + P->b3;
+            const float o = mlp_forward_wave(frag, zst, lane) + mc->b3;
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 v[q] = pst[q * 256 + tid];
@@ -334,7 +334,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             // a cell whose network activations left the FP16 range (|x| >
             // 65504) gets a non-finite output: it falls back like an
             // out-of-range cell
-            learned = P->scale * mlp_softplus(o);
+            learned = mc->scale * mlp_softplus(o);
             use = in_range && __builtin_isfinite(learned);
         }
         if (use) nut = (C)learned;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
     double unused[3] = {0.0, 0.0, 0.0};
     unsigned nofb = 0;
-    step_tile<ST, false, VAR>(a, tile, MlpFrag{}, nullptr, sh, unused, nullptr, nofb);
+    step_tile<ST, false, VAR>(a, tile, MlpFrag{}, nullptr, nullptr, sh, unused, nullptr, nofb);
 }
 
 // Learned closure: persistent blocks keep the network's weight fragments in
@@ -545,13 +545,19 @@ void lbm_step_mlp_kernel(const StepArgs a) {
     if (blockIdx.x == 0 && tid == 0) P->fallback[a.fb_slot ^ 1] = 0;
     __shared__ half8 w2s[4 * 2 * 64];
     mlp_stage_w2(P, w2s, tid, 256);
+    // the closure scalars in LDS: read per tile with LDS loads instead of
+    // occupying scalar registers for the whole walk
+    __shared__ MlpConst mcs;
+    static_assert(sizeof(MlpConst) % 4 == 0 && sizeof(MlpConst) / 4 <= 256, "one float per thread");
+    if (tid < (int)(sizeof(MlpConst) / 4))
+        reinterpret_cast<float *>(&mcs)[tid] = reinterpret_cast<const float *>(&a.mc)[tid];
     __syncthreads();
     const MlpFrag frag = mlp_load_frag(P, tid & 63, w2s);
     double imp[3] = {0.0, 0.0, 0.0};
     unsigned fallbacks = 0;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int tile = (a.flags & FLAG_XCD_REMAP) ? xcd_remap(it, a.ntiles) : it;
-        step_tile<ST, true, VAR>(a, tile, frag, zst[tid >> 6], sh, imp, pst, fallbacks);
+        step_tile<ST, true, VAR>(a, tile, frag, &mcs, zst[tid >> 6], sh, imp, pst, fallbacks);
     }
     // cells that fell back: one atomic per wave
     unsigned fsum = fallbacks;

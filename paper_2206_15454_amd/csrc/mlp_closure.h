@@ -10,10 +10,10 @@
 // same way in the weights: no data moves between lanes from layer to layer.
 //   layer 1: mfma 16x16x16 bf16, A = [W1 | b1_hi b1_lo | 0] (16 units x 16 k),
 //            B = [z0..z8, 1, 1, 0..] of 16 cells
-//   layer 2: mfma 16x16x32 f16 (two k steps), A = W2/2 (FP16) with permuted
-//            k, C initialised with b2 (the inputs are 2 gelu, FP16)
-//   output : o = b3 + (w3/2) . 2gelu(h2) (FP16 pairs, dot2 into FP32, then a
-//            sum over the four lane quarters of a column)
+//   layer 2: mfma 16x16x32 f16 (two k steps), A = W2 (FP16) with permuted
+//            k, C initialised with b2 (the inputs are gelu(h1), FP16)
+//   output : o = b3 + w3 . gelu(h2) (FP16 pairs, dot2 into FP32, then a sum
+//            over the four lane quarters of a column)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,7 +30,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kMlpIn = 9, kMlpH1 = 64, kMlpH2 = 64;
 constexpr int kMlpParams = kMlpH1 * kMlpIn + kMlpH1 + kMlpH2 * kMlpH1 + kMlpH2 + kMlpH2 + 1;
 
-// Packed device parameters (written by mlp_pack on the host).
+// Packed device parameters (written by mlp_pack_blob on the host).  The
+// standardisation, range and output scalars also travel in the step's kernel
+// arguments (MlpConst), where the kernel reads them with scalar loads.
 struct MlpParams {
     float mean[12], istd[12], lo[12], hi[12];  // raw-feature standardisation and range
     float scale, inv_h, b3, pad0;
@@ -79,43 +81,30 @@ __device__ __forceinline__ void mlp_stage_w2(const MlpParams *p, half8 *w2_lds, 
     for (int i = tid; i < 4 * 2 * 64; i += nthreads) w2_lds[i] = src[i];
 }
 
-// Twice the GELU (tanh form x/2 (1 + tanh(a)), a = sqrt(2/pi)(x + 0.044715 x^3)),
-// without transcendentals: 2 gelu(x) = x + x tanh(a(x)); the even function
-// x tanh(a(x)) is a polynomial in y = x^2 on y <= 3.4^2 (least-squares,
-// near-minimax degree 5) and |x| beyond.  Max |error| of gelu: 9.3e-4, below
-// the bf16 rounding of the activations it feeds.  The factor 1/2 is folded
-// exactly into the next layer's weights (W2/2, w3/2) when the blob is packed.
-__device__ __forceinline__ float mlp_gelu2(float x) {
-    const float y = x * x;
-    float e = 2.013099584e-05f;
-    e = __builtin_fmaf(e, y, -7.981360541e-04f);
-    e = __builtin_fmaf(e, y, 1.303727739e-02f);
-    e = __builtin_fmaf(e, y, -1.175806001e-01f);
-    e = __builtin_fmaf(e, y, 7.844402790e-01f);
-    e = __builtin_fmaf(e, y, 1.860028133e-03f);
-    e = (y <= 11.56f) ? e : __builtin_fabsf(x);
-    return x + e;
-}
-
-// The same in packed FP16, in a form that stays well conditioned in 11-bit
-// arithmetic: with a = |x|, 2 gelu(x) = x + a - G(a), G(a) = a (1 - tanh(a(a)))
-// decays to 0; G is a degree-6 polynomial in a on a <= 3.4 (minimax-weighted
-// least squares, no constant term, coefficients rounded to FP16 from the top
-// down and the rest refitted) and is held at G(3.4) ~ 2e-3 beyond.  Max
-// |error| of gelu in FP16 arithmetic: 5.0e-3 (at the cut), the size of the
-// BF16 rounding of an activation near 3.4.  Two values per instruction.
-__device__ __forceinline__ half2v mlp_gelu2_h2(half2v x) {
-    const half2v a = __builtin_elementwise_abs(x);
-    const half2v c = {(_Float16)3.4f, (_Float16)3.4f};
-    const half2v t = __builtin_elementwise_min(a, c);
+// GELU (tanh form x/2 (1 + tanh(a)), a = sqrt(2/pi)(x + 0.044715 x^3)) in
+// packed FP16, two values per instruction: gelu(x) = x s(x) with the gate
+// s = (1 + tanh a)/2 in [0, 1], written s = clamp(1/2 + x P(x^2), 0, 1).  P
+// is a degree-4 polynomial fitted on |x| <= 3 (minimax-weighted least
+// squares of the gelu error; coefficients rounded to FP16 from the top down,
+// the lower ones refitted after each rounding).  Beyond the fit the odd
+// polynomial x P(x^2) grows past 1/2 in magnitude (its leading coefficient
+// is positive), so the clamp saturates the gate at 1 or 0; where x^2
+// overflows FP16 it does so through infinities, never NaN for finite x.  The
+// clamp is the instruction's clamp bit.  Max |error| of gelu over every
+// finite FP16 input, in FP16 arithmetic: 3.3e-3 (at x = 3.03), below the
+// FP16/BF16 rounding of the activations near 3.  Seven instructions per
+// pair.  The degree-4 coefficient is an FP16 subnormal (FP16 denormals are
+// preserved on this target).
+__device__ __forceinline__ half2v mlp_gelu_h2(half2v x) {
     auto k = [](float v) { return half2v{(_Float16)v, (_Float16)v}; };
-    half2v g = k(0.004772186279296875f);
-    g = __builtin_elementwise_fma(g, t, k(-0.0460205078125f));
-    g = __builtin_elementwise_fma(g, t, k(0.12420654296875f));
-    g = __builtin_elementwise_fma(g, t, k(0.0909423828125f));
-    g = __builtin_elementwise_fma(g, t, k(-0.87255859375f));
-    g = __builtin_elementwise_fma(g, t, k(1.0166015625f));
-    return (x + a) - g * t;
+    const half2v y = x * x;
+    half2v p = __builtin_elementwise_fma(y, k(1.710653305053711e-05f), k(-5.578994750976562e-04f));
+    p = __builtin_elementwise_fma(p, y, k(7.762908935546875e-03f));
+    p = __builtin_elementwise_fma(p, y, k(-6.2744140625e-02f));
+    p = __builtin_elementwise_fma(p, y, k(3.96728515625e-01f));
+    half2v s = __builtin_elementwise_fma(x, p, k(0.5f));
+    s = __builtin_elementwise_min(__builtin_elementwise_max(s, k(0.0f)), k(1.0f));
+    return x * s;
 }
 
 __device__ __forceinline__ float mlp_softplus(float x) {
@@ -165,43 +154,57 @@ __device__ __forceinline__ void mlp_stage_inputs(short *lds, int lane, const sho
     *reinterpret_cast<short8v *>(lds + lane * 16 + 8) = hi;
 }
 
-// o (pre-softplus output, without b3) for this lane's cell
+// o (pre-softplus output, without b3) for this lane's cell.  Layer 1 runs for
+// the four 16-cell column tiles first (their FP16 activations stay in
+// registers), so that each layer-2 weight fragment is read from LDS once per
+// 64 cells and serves the four column tiles.  Each lane then holds a partial
+// output of its lane quarter for every column tile; two lane swaps across
+// the wave halves and the quarters (v_permlane32_swap, v_permlane16_swap)
+// sum them so that lane quarter h ends with column tile h.
 __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short *lds, int lane) {
     const int h = lane >> 4, col = lane & 15;
-    float mine = 0.0f;
+    half8 x2[4][2];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const short4v zb = *reinterpret_cast<const short4v *>(lds + (16 * ct + col) * 16 + 4 * h);
-        half8 x2[2];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
             floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[u], zb, zero, 0, 0, 0);
-            const half2v g0 = mlp_gelu2_h2(half2v{(_Float16)d[0], (_Float16)d[1]});
-            const half2v g1 = mlp_gelu2_h2(half2v{(_Float16)d[2], (_Float16)d[3]});
+            const half2v g0 = mlp_gelu_h2(half2v{(_Float16)d[0], (_Float16)d[1]});
+            const half2v g1 = mlp_gelu_h2(half2v{(_Float16)d[2], (_Float16)d[3]});
             const int o = (u & 1) * 4;
-            x2[u >> 1][o] = g0[0];
-            x2[u >> 1][o + 1] = g0[1];
-            x2[u >> 1][o + 2] = g1[0];
-            x2[u >> 1][o + 3] = g1[1];
+            x2[ct][u >> 1][o] = g0[0];
+            x2[ct][u >> 1][o + 1] = g0[1];
+            x2[ct][u >> 1][o + 2] = g1[0];
+            x2[ct][u >> 1][o + 3] = g1[1];
         }
-        float part = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(f.w2[(2 * u) * 64 + lane], x2[0],
-                                                               f.b2[u], 0, 0, 0);
-            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(f.w2[(2 * u + 1) * 64 + lane], x2[1], e,
-                                                       0, 0, 0);
-            const half2v g0 = mlp_gelu2_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
-            const half2v g1 = mlp_gelu2_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
-            part = __builtin_amdgcn_fdot2(g0, f.w3[u][0], part, false);
-            part = __builtin_amdgcn_fdot2(g1, f.w3[u][1], part, false);
-        }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (h == ct) mine = part;
     }
-    return mine;
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const half8 wa = f.w2[(2 * u) * 64 + lane], wb = f.w2[(2 * u + 1) * 64 + lane];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa, x2[ct][0], f.b2[u], 0, 0, 0);
+            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(wb, x2[ct][1], e, 0, 0, 0);
+            const half2v g0 = mlp_gelu_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
+            const half2v g1 = mlp_gelu_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
+            part[ct] = __builtin_amdgcn_fdot2(g0, f.w3[u][0], part[ct], false);
+            part[ct] = __builtin_amdgcn_fdot2(g1, f.w3[u][1], part[ct], false);
+        }
+    }
+    // halves: lanes 0-31 keep column tiles 0 and 1, lanes 32-63 tiles 2 and 3
+    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
+                                                      __float_as_uint(part[2]), false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[1]),
+                                                      __float_as_uint(part[3]), false, false);
+    const float a02 = __uint_as_float(s02[0]) + __uint_as_float(s02[1]);
+    const float a13 = __uint_as_float(s13[0]) + __uint_as_float(s13[1]);
+    // quarters: the lower 16 lanes of each half keep the even tile, the upper the odd
+    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(a02), __float_as_uint(a13),
+                                                    false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
 }
 
 }  // namespace lbmx

@@ -15,9 +15,9 @@ namespace lbmx {
 constexpr size_t kMlpDeviceBytes = 32768;
 
 // Validate a closure blob and pack it into the device layout (dev:
-// kMlpDeviceBytes).  false with a reason for a bad magic, version, shape or
-// size.
-bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why);
+// kMlpDeviceBytes) and the step's kernel-argument scalars (mc).  false with
+// a reason for a bad magic, version, shape or size.
+bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, MlpConst *mc, std::string *why);
 
 // fused step with the learned closure: a persistent kernel of `grid` blocks
 // (mlp_launch_grid: the blocks that fit on the device at once, a multiple of

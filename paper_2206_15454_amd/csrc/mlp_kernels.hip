@@ -61,7 +61,7 @@ float from_bf16_bits(uint16_t b) {
 
 }  // namespace
 
-bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why) {
+bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, MlpConst *mc, std::string *why) {
     auto fail = [&](const char *m) {
         if (why) *why = m;
         return false;
@@ -111,9 +111,9 @@ bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why)
             for (int l = 0; l < 64; ++l)
                 for (int t = 0; t < 8; ++t) {
                     const int uo = 16 * ut + l % 16, ui = mlp_l2_unit_in(ks, l / 16, t);
-                    // halved: the device activations are 2 gelu; FP16 holds every
-                    // halved BF16 weight of magnitude >= 2^-14 exactly
-                    const float wv = 0.5f * from_bf16_bits(u16_at(b, w2o + 2 * (uo * kMlpH1 + ui)));
+                    // FP16 holds every BF16 weight of magnitude in [2^-14, 65504]
+                    // exactly
+                    const float wv = from_bf16_bits(u16_at(b, w2o + 2 * (uo * kMlpH1 + ui)));
                     P.w2f[ut][ks][l][t] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
                 }
     for (int ut = 0; ut < 4; ++ut)
@@ -121,10 +121,19 @@ bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, std::string *why)
             for (int r = 0; r < 4; ++r) {
                 const int u = 16 * ut + 4 * hq + r;
                 P.b2f[ut][hq][r] = f32_at(b, 184 + 256 + 4 * u);
-                const float wv = 0.5f * from_bf16_bits(u16_at(b, w3o + 2 * u));
+                const float wv = from_bf16_bits(u16_at(b, w3o + 2 * u));
                 P.w3h[ut][hq][r / 2][r % 2] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
             }
     std::memcpy(dev, &P, sizeof(P));
+    for (int i = 0; i < kMlpIn; ++i) {
+        mc->zs[i] = P.istd[i];
+        mc->zo[i] = -P.mean[i] * P.istd[i];
+        mc->lo[i] = P.lo[i];
+        mc->hi[i] = P.hi[i];
+    }
+    mc->inv_h = P.inv_h;
+    mc->scale = P.scale;
+    mc->b3 = P.b3;
     return true;
 }
 

@@ -73,3 +73,73 @@ def test_channel_matches_oracle_and_stays_mirror_symmetric():
     scale = np.max(np.abs(ug[0]))
     assert np.max(np.abs(ug[0] - ug[0][:, ::-1, :])) <= 1e-12 * scale
     assert np.max(np.abs(ug[1] + ug[1][:, ::-1, :])) <= 1e-12 * scale
+
+
+def test_channel_total_stress_balances_the_driving_force():
+    """The Re_tau = 180 channel of Sec. 4 on its own mesh (372x62x124, FP32),
+    driven by the body force of Eq. (Body_force), F = rho u_tau^2 / H with
+    H = ny/2.  Averaging the x-momentum equation over x, z and a window of T
+    steps and integrating it from the mid-plane (where the total shear
+    stress vanishes by symmetry) gives, at height y of the lower half,
+
+        -<u'v'> + (nu0 + <nu_t>) d<u>/dy = g (H - y) - (1/T) int_y^H D<u> dy',
+
+    D<u> the change of the plane-mean velocity over the window.  In a
+    statistically steady state the last term vanishes and the wall value of
+    the stress is u_tau^2 = g H; here the flow is still developing and the
+    term is kept (it is measured, not modelled).  The stress comes from the
+    plane statistics (sampled every 10 steps), the velocity gradient from
+    central differences of the mean profile, nu_t enters through its plane
+    mean.  Bounds: 3 % of u_tau^2 on every row but the two next to each wall
+    (measured 1.4 %), antisymmetry of the upper half 2 % (measured 0.5 %)."""
+    import torch
+
+    w = inputs.CHANNEL
+    g = make_gpu(w, "f32")
+    rho, u = inputs.init_fields(w)
+    g.init(rho, u)
+    g.step(20000)
+
+    def plane_mean_u():
+        return g.moments()[1][0].mean(axis=(0, 2))
+
+    u1 = plane_mean_u()
+    window = 60000
+    g.stats_reset()
+    g.stats_enable(10)
+    g.step(window)
+    u2 = plane_mean_u()
+    prof, ns = g.stats_read()
+    torch.cuda.synchronize()
+    assert ns == window // 10
+    ny = w.ny
+    H = ny / 2
+    gx = w.g[0]
+    nu0 = (w.tau0 - 0.5) / 3
+    ut2 = gx * H
+    U, V, UV, NUT = prof[:, 0], prof[:, 1], prof[:, 6], prof[:, 9]
+    rows = np.arange(2, ny - 2)
+    tau = -(UV[rows] - U[rows] * V[rows]) + (nu0 + NUT[rows]) * (U[rows + 1] - U[rows - 1]) / 2
+    dudt = (u2 - u1) / window
+    expect = np.zeros(ny)
+    for j in range(ny // 2):
+        m = ny - 1 - j
+        drive = gx * (H - (j + 0.5))
+        expect[j] = drive - (0.5 * dudt[j] + dudt[j + 1: ny // 2].sum())
+        expect[m] = -(drive - (0.5 * dudt[m] + dudt[ny // 2: m].sum()))
+    err = np.max(np.abs(tau - expect[rows])) / ut2
+    half = ny // 2 - 2
+    asym = np.max(np.abs(tau[:half] + tau[::-1][:half])) / ut2
+    # the measured stress with the unsteady term added back is linear in y:
+    # slope -g, wall value u_tau^2 = g H (lower half, rows 2..H-1)
+    lower = rows[rows < ny // 2]
+    unsteady = np.array([0.5 * dudt[j] + dudt[j + 1: ny // 2].sum() for j in lower])
+    slope, wall = np.polyfit(lower + 0.5, tau[: len(lower)] + unsteady, 1)
+    print(f"bulk u {U.mean():.5f}, u_tau {np.sqrt(ut2):.3e}; max |tau - budget| / u_tau^2 {err:.4f}; "
+          f"asymmetry {asym:.4f}; fit: slope / g {-slope / gx:.4f}, wall stress / (g H) "
+          f"{wall / ut2:.4f}; resolved -u'v' at row 4: {-(UV[4] - U[4] * V[4]) / ut2:.3f} u_tau^2")
+    assert abs(-slope / gx - 1.0) <= 0.03
+    assert abs(wall / ut2 - 1.0) <= 0.03
+    assert err <= 0.03
+    assert asym <= 0.02
+    g.close()
