@@ -163,6 +163,9 @@ def main():
     ap.add_argument("--mlp-canopy-every", default="1,8",
                     help="intervals timed with the closure restricted to the canopy layer "
                          "(y/h <= 4, Smagorinsky above)")
+    ap.add_argument("--c5", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 1024x256x512 pair of the learned-closure comparison: "
+                         "FP32 + Smagorinsky against low-precision storage + learned closure")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -264,6 +267,40 @@ def main():
             variants[name] = {"MLUPS": round(v, 1), "vs_" + args.storage: round(v / mlups, 3),
                               "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4),
                               "closure_every": every, "mlp_fallback": d["mlp_fallback"]}
+
+    if args.c5 and args.workload == "c2":
+        # the learned-closure comparison at its configured size (1024x256x512,
+        # the 64x32x32 case's physics): FP32 + Smagorinsky, then the
+        # low-precision storage without the network, and with it evaluated
+        # every step and every 4th step.  The trained network with its input
+        # ranges opened, so that every cell evaluates it here too.
+        from paper_2206_15454_amd import closure
+
+        net = closure.everywhere(closure.trained_blob())
+        w5 = inputs.C5
+        rho5, u5 = inputs.init_fields_torch(w5, torch.device("cuda"))
+        k = max(50, args.steps // 10)
+        c5 = {}
+        for name, st, blob, every in (("f32", "f32", None, 1),
+                                      (args.mlp_storage, args.mlp_storage, None, 1),
+                                      (args.mlp_storage + "+mlp", args.mlp_storage, net, 1),
+                                      (args.mlp_storage + "+mlp/4", args.mlp_storage, net, 4)):
+            sim = make_sim(w5, st, lbm, inputs)
+            sim.init(rho5, u5)
+            if blob is not None:
+                sim.set_closure(blob)
+                sim.set_closure_interval(every)
+            t_ms, s_ms, d = time_steps(sim, k, 10, torch)
+            sim.close()
+            c5[name] = {"MLUPS": round(w5.n * k / (t_ms * 1e-3) / 1e6, 1),
+                        "hbm_frac": round((2 * 19 * BYTES_PER_ELT[st] + (4 if every > 1 else 0))
+                                          * w5.n / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4)}
+            if blob is not None:
+                c5[name]["mlp_fallback"] = d["mlp_fallback"]
+        for name in c5:
+            c5[name]["vs_f32"] = round(c5[name]["MLUPS"] / c5["f32"]["MLUPS"], 3)
+        variants["c5:1024x256x512"] = c5
+        del rho5, u5
 
     out = {
         "metric": METRIC,

@@ -97,6 +97,14 @@ def with_range(blob, feature, lo=None, hi=None):
     return make_blob(p, mean, std, rlo, rhi, scale, h)
 
 
+def everywhere(blob):
+    """The same network with every input range opened: every cell evaluates
+    it (no Smagorinsky fallback except for non-finite outputs).  For timing
+    it on workloads other than the one it was trained on."""
+    p, mean, std, _, _, scale, h = read_blob(blob)
+    return make_blob(p, mean, std, np.full(NIN, -3e38), np.full(NIN, 3e38), scale, h)
+
+
 def timing_blob(canopy_h, seed=0):
     """A random network whose input ranges admit every cell (for timing the
     closure kernel; its nu_t is small and positive)."""

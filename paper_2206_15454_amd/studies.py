@@ -15,6 +15,10 @@
       its feature range; Smagorinsky above) against the unrestricted one.
   python -m paper_2206_15454_amd.studies abl --out DIR
       the paper's ABL cases 1-3 (350x140x280): mean profiles, u_* at y/h = 2.
+  python -m paper_2206_15454_amd.studies aposteriori --out DIR
+      the whole learned-closure pipeline at half size (fine 512x128x256 ->
+      filter -> GPU training -> coarse 256x64x128 with each closure) and the
+      profile errors of both closures against the filtered fine statistics.
   python -m paper_2206_15454_amd.studies precision --out DIR
       storage precision on 1024x256x512 (physics of the 64x32x32 canopy
       case): FP32 / FP16S / BF16S fields after 1000 steps against the GPU FP64
@@ -544,10 +548,139 @@ def apriori_study(out, fine_steps=20000, batch=8192):
     return res
 
 
+def aposteriori_pipeline(fine_steps=20000, tau0=0.5005, epochs=3, batch=8192, lr=1e-3,
+                         storages=("f32", "bf16sr"), out=None):
+    """The whole learned-closure pipeline at half the production size, and
+    what the trained network gains a posteriori over the Smagorinsky closure
+    of Sec. 2.2.  Coarse case: the production canopy set-up on 256x64x128
+    cells (h = 6 cells, LAI 2, C_D = 0.15, u_tau = 0.01, g = u_tau^2 / ny,
+    bounce-back ground, free-slip top); reference: the same physics at twice
+    the resolution, 512x128x256 (h = 12, acoustic scaling: tau0_f = 1/2 +
+    2 (tau0 - 1/2), g_f = g/2), FP32 + Smagorinsky, fine_steps steps with
+    statistics over the second half (every 20 steps) and training samples at
+    three snapshots of that half (2x2x2 box filter; 90/10 split by z slab).
+    The network is trained on the GPU (Adam, `epochs` passes).  The coarse
+    runs (fine_steps / 2 steps, statistics over the second half every 10
+    steps) start from one seeded field, with each closure in each storage.
+    Returns the profile errors of each coarse run against the box-filtered
+    fine statistics, split at y/h = 4 (canopy layer and upper layer), and the
+    x-z RMS density fluctuation per row at the end of each run, which shows
+    the grid-scale mode that the BGK collision carries in the upper layer at
+    this tau0 and Mach number."""
+    import torch
+    from dataclasses import replace
+
+    dev = torch.device("cuda")
+    ut = 0.01
+    wc = replace(inputs.C2, name="canopy-abl-256x64x128", nx=256, ny=64, nz=128, tau0=tau0,
+                 g=(ut ** 2 / 64, 0.0, 0.0), lad_lalic=(6.0, 4.2, 2.0), y_ref=64.0, seed=12)
+    wf = replace(inputs.C2, name="canopy-abl-fine-512x128x256", nx=512, ny=128, nz=256,
+                 tau0=0.5 + 2.0 * (tau0 - 0.5), g=(ut ** 2 / 64 / 2.0, 0.0, 0.0),
+                 lad_lalic=(12.0, 8.4, 2.0), y_ref=128.0, seed=13)
+    h_c = wc.lad_lalic[0]
+    lad_c = _lad(wc)
+    res = {"coarse": wc.name, "fine": wf.name, "u_tau": ut, "fine_steps": fine_steps}
+    t0 = time.time()
+    rho, u = inputs.init_fields_torch(wf, dev)
+    fine = make(wf, "f32", rho, u)
+    del rho, u
+    half = fine_steps // 2
+    fine.step(half)
+    fine.stats_reset()
+    fine.stats_enable(20)
+    Xs, ys = [], []
+    done = half
+    for snap in (half + half // 3, half + 2 * half // 3, fine_steps):
+        fine.step(snap - done)
+        done = snap
+        X, y = fine.closure_samples(wc.tau0, h_c, lad_c)
+        Xs.append(X)
+        ys.append(y)
+    prof_f, _ = fine.stats_read()
+    r, _, _, d = fine.moments()
+    rho_rms_fine = 0.5 * (r.std(axis=(0, 2))[0::2] + r.std(axis=(0, 2))[1::2])
+    fine.close()
+    ref = coarsen_profile(prof_f)
+    _log(f"fine run {time.time() - t0:.1f} s, max |u| {d['max_u']:.3f}")
+
+    per = Xs[0].shape[0]
+    cut = per * 9 // 10
+    Xtr = torch.cat([x[:cut] for x in Xs]).cpu().numpy()
+    ytr = torch.cat([y[:cut] for y in ys]).cpu().numpy()
+    Xva = torch.cat([x[cut:] for x in Xs])
+    yva = torch.cat([y[cut:] for y in ys])
+    del Xs, ys
+    mean = Xtr.mean(axis=0, dtype=np.float64)
+    std = Xtr.std(axis=0, dtype=np.float64)
+    std[std <= 0] = 1.0
+    lo = Xtr.min(axis=0).astype(np.float64)
+    hi = Xtr.max(axis=0).astype(np.float64)
+    s = float(ytr.mean()) if ytr.mean() > 0 else 1e-5
+    var = float(np.var(ytr / s))
+    rng = np.random.default_rng(7)
+    idx = rng.permutation(Xtr.shape[0])
+    Xd = torch.from_numpy(np.ascontiguousarray(Xtr[idx])).to(dev)
+    yd = torch.from_numpy(np.ascontiguousarray(ytr[idx])).to(dev)
+    del Xtr, ytr
+    p0 = closure.join(rng.normal(size=(64, 9)) / 3.0, np.zeros(64),
+                      rng.normal(size=(64, 64)) / 8.0, np.zeros(64),
+                      rng.normal(size=64) / 8.0, math.log(math.e - 1.0))
+    tr = lbm.Trainer(p0, mean, std, s, lr=lr, max_batch=batch)
+    nb = Xd.shape[0] // batch
+    for _ in range(epochs):
+        for b in range(nb):
+            tr.step(Xd[b * batch:(b + 1) * batch], yd[b * batch:(b + 1) * batch], update=True,
+                    loss=False)
+    vls = [tr.step(Xva[b:b + batch], yva[b:b + batch], update=False)
+           for b in range(0, yva.numel() - batch + 1, batch * 4)]
+    p, _ = tr.get()
+    tr.close()
+    blob = closure.make_blob(p, mean, std, lo, hi, s, h_c)
+    res["train"] = {"samples": int(Xd.shape[0]), "epochs": epochs, "target_mean": s,
+                    "val_explained_variance": 1.0 - float(np.mean(vls)) / var}
+    del Xd, yd, Xva, yva
+    _log(f"trained {time.time() - t0:.1f} s: {res['train']}")
+
+    yh = (np.arange(wc.ny) + 0.5) / h_c
+    layers = {"canopy": yh <= 4.0, "upper": yh > 4.0}
+    pr = profiles(ref)
+    res["reference_rho_rms"] = rho_rms_fine.tolist()
+    rho, u = inputs.init_fields_torch(wc, dev)
+    cs = fine_steps // 2
+    runs = {}
+    for st in storages:
+        for name, b in (("smag", None), ("mlp", blob)):
+            sim = make(wc, st, rho, u, b)
+            sim.step(cs // 2)
+            sim.stats_reset()
+            sim.stats_enable(10)
+            sim.step(cs - cs // 2)
+            prof, _ = sim.stats_read()
+            r, _, _, d = sim.moments()
+            sim.close()
+            pa = profiles(prof)
+            errs = {}
+            for ln, m in layers.items():
+                errs[ln] = {k: float(np.max(np.abs(pa[k][m] - pr[k][m])) / np.max(np.abs(pr[k])))
+                            for k in ("u", "u_rms", "v_rms", "w_rms", "uv")}
+            runs[f"{st}_{name}"] = {"errors_vs_filtered_fine": errs,
+                                    "rho_rms": r.std(axis=(0, 2)).tolist(),
+                                    "nu_t_mean": float(np.mean(pa["nu_t"])),
+                                    "mlp_fallback": d["mlp_fallback"], "max_u": d["max_u"],
+                                    "u": pa["u"].tolist()}
+    res["runs"] = runs
+    res["y_over_h"] = yh.tolist()
+    _log(f"coarse runs {time.time() - t0:.1f} s")
+    if out:
+        with open(os.path.join(out, "aposteriori_pipeline.json"), "w") as f:
+            json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["closure", "precision", "interval", "abl", "small", "layer",
-                                      "apriori"])
+                                      "apriori", "aposteriori"])
     ap.add_argument("--out", default="studies_out")
     ap.add_argument("--fine-steps", type=int, default=40000)
     ap.add_argument("--coarse-steps", type=int, default=20000)
@@ -577,6 +710,8 @@ def main():
                     avg_from=args.avg_from or args.coarse_steps // 2)
     elif args.study == "apriori":
         apriori_study(args.out, fine_steps=args.fine_steps // 2)
+    elif args.study == "aposteriori":
+        aposteriori_pipeline(fine_steps=args.fine_steps // 2, out=args.out)
     else:
         abl_study(args.out, steps=args.long_steps, avg_from=args.avg_from or args.long_steps // 2)
 
