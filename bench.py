@@ -113,6 +113,45 @@ def time_steps(sim, steps, warmup, torch):
     return e0.elapsed_time(e2), e0.elapsed_time(e1), d
 
 
+def time_training(torch, lbm, batch=8192, steps=200, big=1 << 20):
+    """Closure training throughput on synthetic samples of the training
+    set's shape (X [n][9] FP32, y [n]): Adam steps at the training batch, and
+    one gradient evaluation over `big` samples (no update).  Algorithmic
+    work: forward + backward = 3 x 9472 flop per sample."""
+    import numpy as np
+
+    from paper_2206_15454_amd import closure
+
+    g = torch.Generator(device="cuda").manual_seed(5)
+    X = torch.randn(big, 9, device="cuda", generator=g)
+    y = torch.rand(big, device="cuda", generator=g) * 1e-3
+    p, mean, std, _, _, s, _ = closure.read_blob(closure.trained_blob())
+    tr = lbm.Trainer(p, np.zeros(9), np.ones(9), s, max_batch=big)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for b in range(20):
+        tr.step(X[b * batch:(b + 1) * batch], y[b * batch:(b + 1) * batch], update=True, loss=False)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for b in range(steps):
+        o = (b % 100) * batch
+        tr.step(X[o:o + batch], y[o:o + batch], update=True, loss=False)
+    ev[1].record()
+    tr.step(X, y, update=False, loss=False)
+    torch.cuda.synchronize()
+    ev[2].record()
+    tr.step(X, y, update=False, loss=False)
+    ev[3].record()
+    torch.cuda.synchronize()
+    tr.close()
+    t_steps = ev[0].elapsed_time(ev[1]) * 1e-3
+    t_big = ev[2].elapsed_time(ev[3]) * 1e-3
+    flop = 3 * 9472
+    return {"adam_steps_batch": batch, "samples_per_s": round(steps * batch / t_steps),
+            "us_per_step": round(t_steps / steps * 1e6, 1),
+            "gradient_pass_samples": big, "gradient_samples_per_s": round(big / t_big),
+            "gradient_tflops": round(big * flop / t_big / 1e12, 2)}
+
+
 def cpu_baseline(w, target_s=10.0):
     """The FP64 oracle on a z-slab of the same workload (all host cores)."""
     import numpy as np
@@ -166,6 +205,9 @@ def main():
     ap.add_argument("--c5", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 1024x256x512 pair of the learned-closure comparison: "
                          "FP32 + Smagorinsky against low-precision storage + learned closure")
+    ap.add_argument("--train", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the closure training kernels (Adam steps at batch 8192 and "
+                         "a gradient pass over 1M samples)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -301,6 +343,9 @@ def main():
             c5[name]["vs_f32"] = round(c5[name]["MLUPS"] / c5["f32"]["MLUPS"], 3)
         variants["c5:1024x256x512"] = c5
         del rho5, u5
+
+    if args.train and args.workload == "c2":
+        variants["train:9-64-64-1"] = time_training(torch, lbm)
 
     out = {
         "metric": METRIC,

@@ -103,7 +103,8 @@ typedef struct lbm_diag {
  * (edge).  c: [19][3], w: [19] (either may be NULL).  Returns 19. */
 int32_t lbm_lattice(int32_t *c, double *w);
 
-/* Device bytes one context needs (populations, moments, partial sums).
+/* Device bytes one context needs (populations, moments, partial sums; the
+ * population rows padded to whole 128-byte lines, see lbm_create).
  * Returns 0 for invalid parameters. */
 size_t lbm_required_bytes(const lbm_params *p);
 
@@ -128,7 +129,11 @@ size_t lbm_required_bytes(const lbm_params *p);
  *                           row is a whole number of 128-byte lines)
  *   LBMX_TILE_ORDER=0|1     row-major or memory-order tile numbering (default:
  *                           memory order unless rows stream and a plane is at
- *                           most 96 MiB) */
+ *                           most 96 MiB)
+ *   LBMX_PITCH=0|1          population rows padded to whole 128-byte lines
+ *                           (default 1: rows of nx cells that are not whole
+ *                           lines get a pitch of the next whole number of
+ *                           lines; the pad cells are never touched) */
 lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out);
 
 /* Release the context (and its device memory if the library allocated it). */

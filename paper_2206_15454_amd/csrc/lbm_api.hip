@@ -29,6 +29,7 @@ struct lbm_ctx {
     size_t elt = 0;      // bytes per stored population
     size_t celt = 0;     // bytes per arithmetic value
     long long qs = 0;    // population plane stride, elements
+    int px = 0;          // population row pitch, cells (>= nx)
     // launch geometry
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;
@@ -157,6 +158,22 @@ long long plane_stride(long long n, size_t elt) {
     return qs;
 }
 
+// Population row pitch: rows padded to whole 128-byte lines, so that every
+// row starts on a line and the row-aligned accesses can stream (rows of 350
+// FP32 cells, 1 400 B, otherwise share their end lines with the next row).
+// The padding cells are never read or written.  No padding when a row is
+// already whole lines or the padded array would not be indexable in 32 bits;
+// LBMX_PITCH=0 disables it (the populations are bit-identical either way).
+int row_pitch(const lbm_params *p) {
+    const long long elt = (long long)storage_bytes(p->storage);
+    const long long per_line = 128 / elt;
+    long long px = (p->nx + per_line - 1) / per_line * per_line;
+    if (const char *e = std::getenv("LBMX_PITCH"))
+        if (std::atoi(e) == 0) px = p->nx;
+    if (px * p->ny * p->nz >= (1LL << 31)) px = p->nx;
+    return (int)px;
+}
+
 struct Layout {
     size_t f, mom, lad, imp, dg, stats, red, prof, mlp, fidx, ftab, ftabf, total;
 };
@@ -169,7 +186,7 @@ Layout layout(const lbm_params *p) {
     int bx, bz, nbx, nbz;
     geometry(p, &bx, &bz, &nbx, &nbz);
     const long long ntiles = (long long)nbx * nbz * p->ny;
-    const long long qs = plane_stride(n, elt);
+    const long long qs = plane_stride((long long)row_pitch(p) * p->ny * p->nz, elt);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -248,7 +265,8 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->n = (long long)p->nx * p->ny * p->nz;
     c->elt = storage_bytes(p->storage);
     c->celt = p->storage == LBM_F64 ? 8 : 4;
-    c->qs = plane_stride(c->n, c->elt);
+    c->px = row_pitch(p);
+    c->qs = plane_stride((long long)c->px * p->ny * p->nz, c->elt);
     geometry(p, &c->bx, &c->bz, &c->nbx, &c->nbz);
     c->tpp = c->nbx * c->nbz;
     c->ntiles = c->tpp * p->ny;
@@ -256,7 +274,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     if (const char *e = std::getenv("LBMX_WIDE")) c->force_wide = std::atoi(e) != 0;
     // streaming (non-temporal) accesses where rows are whole 128-byte lines
     // (the planes start on 256-byte boundaries); LBMX_STREAMING=0/1 overrides
-    c->streaming = ((long long)p->nx * (long long)c->elt) % 128 == 0;
+    c->streaming = ((long long)c->px * (long long)c->elt) % 128 == 0;
     if (const char *e = std::getenv("LBMX_STREAMING")) c->streaming = std::atoi(e) != 0;
     // tile order: the tiles that run at the same time span the fewest pages in
     // memory order.  The row-major order measured faster only for streaming
@@ -425,7 +443,7 @@ lbm_status lbm_init(lbm_ctx *c, const double *rho, const double *u, int32_t on_d
         drho = tmp;
         du = tmp + n;
     }
-    HIPCHK(c, launch_init(c->p.storage, c->f, c->qs, c->mom, drho, du, (int)n, c->stream),
+    HIPCHK(c, launch_init(c->p.storage, c->f, c->qs, c->p.nx, c->px, c->mom, drho, du, (int)n, c->stream),
            "lbm_init: kernel");
     if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_init: free staging");
     lbm_status s = reset_accumulators(c);
@@ -451,6 +469,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
+    a.px = c->px;
     a.nbx = c->nbx;
     a.nbz = c->nbz;
     div_magic((uint32_t)a.nbx, &a.m_nbx, &a.s_nbx);
@@ -643,7 +662,7 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *fin, int32_t on_device) {
     }
     // stored where the next step reads it: the AA parity of the context
     // continues (before the first step after lbm_init it is 0)
-    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, c->p.nx, c->p.ny, c->p.nz, c->parity,
+    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, c->p.nx, c->px, c->p.ny, c->p.nz, c->parity,
                            c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_set_f: kernel");
     if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_set_f: free staging");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_f: sync");
@@ -666,7 +685,7 @@ lbm_status lbm_get_f(lbm_ctx *c, double *fout, int32_t on_device) {
                "lbm_get_f: staging");
         dst = tmp;
     }
-    HIPCHK(c, launch_get_f(c->p.storage, c->f, c->qs, dst, c->p.nx, c->p.ny, c->p.nz, c->parity,
+    HIPCHK(c, launch_get_f(c->p.storage, c->f, c->qs, dst, c->p.nx, c->px, c->p.ny, c->p.nz, c->parity,
                            c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_get_f: kernel");
     if (tmp) {
         HIPCHK(c, hipMemcpyAsync(fout, tmp, (size_t)NQ * n * 8, hipMemcpyDeviceToHost, c->stream),

@@ -123,14 +123,19 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // The neighbour's index is the own index plus one offset per axis: x
     // and z wrap per thread (a select), y is uniform per block, so the 18
     // neighbours cost additions only.
-    const int plane = nx * ny;
+    // self: the cell's dense index (moments, forest index, rounding hash);
+    // pself: its population index, rows laid out with the pitch px >= nx
+    // (rows padded to whole cache lines)
+    const int px = a.px;
+    const int plane = px * ny;
     const int self = (kc * ny + j) * nx + ic;
+    const int pself = (kc * ny + j) * px + ic;
     const int xo[3] = {ic == 0 ? nx - 1 : -1, 0, ic == nx - 1 ? 1 - nx : 1};
-    const int yo[3] = {(j == 0 ? ny - 1 : -1) * nx, 0, (j == ny - 1 ? 1 - ny : 1) * nx};
+    const int yo[3] = {(j == 0 ? ny - 1 : -1) * px, 0, (j == ny - 1 ? 1 - ny : 1) * px};
     const int zo[3] = {kc == 0 ? (nz - 1) * plane : -plane, 0,
                        kc == nz - 1 ? (1 - nz) * plane : plane};
     auto cell = [&](int dx, int dy, int dz) -> int {
-        return self + xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
+        return pself + xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
     };
 
     // ---- a1/a2: stream in (AA slot map with walls), decode ----------------
@@ -163,7 +168,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                v[q] = pop.template ld<policy_local<S>()>(q, self);
+                v[q] = pop.template ld<policy_local<S>()>(q, pself);
             });
         } else if (!wall_row) {
             static_for<NQ>([&](auto qc) {
@@ -179,7 +184,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                 if (cy != 0 && (js < 0 || js >= ny) &&
                     (js < 0 ? a.bc_lo : a.bc_hi) != BC_PERIODIC) {
                     if ((js < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                        v[q] = pop.template ld<pol>(q, self);  // left this cell towards the wall
+                        v[q] = pop.template ld<pol>(q, pself);  // left this cell towards the wall
                     else  // free slip: left the wall row upstream, moving towards the wall
                         v[q] = pop.template ld<pol>(opp(mir(q)), cell(-cx, 0, -cz));
                 } else {
@@ -403,7 +408,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         if (a.parity) {
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                pop.template st<policy_local<S>()>(opp(q), self, v[q], rnd(q));
+                pop.template st<policy_local<S>()>(opp(q), pself, v[q], rnd(q));
             });
         } else if (!wall_row) {
             static_for<NQ>([&](auto qc) {
@@ -422,7 +427,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
                     // leaving population in the own cell's opposite slot (a
                     // forced-equilibrium boundary never reads it back)
                     if ((jt < 0 ? a.bc_lo : a.bc_hi) != BC_FREESLIP)
-                        pop.template st<pol>(opp(q), self, v[q], rnd(q));
+                        pop.template st<pol>(opp(q), pself, v[q], rnd(q));
                     else
                         pop.template st<pol>(mir(q), cell(cx, 0, cz), v[q], rnd(q));
                 } else {
@@ -571,14 +576,16 @@ void lbm_step_mlp_kernel(const StepArgs a) {
 // f = feq(rho, u) as post-collision populations, stored shifted in the
 // layout a neighbour step reads (slot opp(q) of the own cell).
 template <int ST>
-__global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, void *mom,
-                                                   const double *rho, const double *u, int n) {
+__global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, int nx, int px,
+                                                   void *mom, const double *rho, const double *u,
+                                                   int n) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     T *f = static_cast<T *>(fp);
+    const long long xp = (long long)(x / nx) * px + x % nx;  // population index (row pitch px)
     const double r = rho[x], ux = u[x], uy = u[n + x], uz = u[2 * (long long)n + x];
     const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
     static_for<NQ>([&](auto qc) {
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, void 
         const double cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
         const double w = weight(q);
         const double fs = w * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - usq15));
-        CD::st(f + opp(q) * qs + x, (C)fs);
+        CD::st(f + opp(q) * qs + xp, (C)fs);
     });
     C *m = static_cast<C *>(mom);
     m[x] = (C)r;
@@ -601,25 +608,26 @@ __global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, void 
 // next) slot opp(q) of x; after a neighbour step (parity 1 next) where the
 // neighbour step wrote it (slot q of x + c_q, or the wall's slot).  A
 // bijection of the 19 N slots (every cell reads and writes the same 19).
-__device__ __forceinline__ long long slot_of(int q, long long x, int i, int j, int k, int nx,
-                                             int ny, int nz, int parity, int bc_lo, int bc_hi,
+__device__ __forceinline__ long long slot_of(int q, int i, int j, int k, int nx, int px, int ny,
+                                             int nz, int parity, int bc_lo, int bc_hi,
                                              long long qs) {
-    if (parity == 0) return opp(q) * qs + x;
+    const long long own = ((long long)k * ny + j) * px + i;  // rows of pitch px
+    if (parity == 0) return opp(q) * qs + own;
     const int cx = CX[q], cy = CY[q], cz = CZ[q];
     const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
     const int jt = j + cy;
     if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
         if ((jt < 0 ? bc_lo : bc_hi) != BC_FREESLIP)  // bounce-back or forced equilibrium
-            return opp(q) * qs + x;
-        return mir(q) * qs + ((long long)kt * ny + j) * nx + it;
+            return opp(q) * qs + own;
+        return mir(q) * qs + ((long long)kt * ny + j) * px + it;
     }
-    return q * qs + ((long long)kt * ny + (jt + ny) % ny) * nx + it;
+    return q * qs + ((long long)kt * ny + (jt + ny) % ny) * px + it;
 }
 
 template <int ST>
 __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, const double *fin,
-                                                    int nx, int ny, int nz, int parity, int bc_lo,
-                                                    int bc_hi) {
+                                                    int nx, int px, int ny, int nz, int parity,
+                                                    int bc_lo, int bc_hi) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
@@ -632,7 +640,7 @@ __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, cons
     const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const long long at = slot_of(q, x, i, j, k, nx, ny, nz, parity, bc_lo, bc_hi, qs);
+        const long long at = slot_of(q, i, j, k, nx, px, ny, nz, parity, bc_lo, bc_hi, qs);
         CD::st(f + at, (C)(fin[(long long)q * n + x] - weight(q)));
     });
 }
@@ -642,7 +650,7 @@ __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, cons
 // (parity 1 next) where the neighbour step wrote them.
 template <int ST>
 __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs, double *fout,
-                                                    int nx, int ny, int nz, int parity,
+                                                    int nx, int px, int ny, int nz, int parity,
                                                     int bc_lo, int bc_hi) {
     using CD = Codec<ST>;
     using T = typename CD::T;
@@ -655,7 +663,7 @@ __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs
     const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const long long at = slot_of(q, x, i, j, k, nx, ny, nz, parity, bc_lo, bc_hi, qs);
+        const long long at = slot_of(q, i, j, k, nx, px, ny, nz, parity, bc_lo, bc_hi, qs);
         fout[q * n + x] = (double)CD::ld(f + at) + weight(q);
     });
 }
@@ -916,26 +924,26 @@ hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, int g
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, void *f, long long qs, void *mom, const double *rho,
-                       const double *u, int n, hipStream_t s) {
+hipError_t launch_init(int storage, void *f, long long qs, int nx, int px, void *mom,
+                       const double *rho, const double *u, int n, hipStream_t s) {
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, mom, rho, u, n));
+                                              s, f, qs, nx, px, mom, rho, u, n));
     return hipGetLastError();
 }
 
-hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int ny,
-                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int px,
+                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, fin, nx, ny, nz, parity, bc_lo, bc_hi));
+                                              s, f, qs, fin, nx, px, ny, nz, parity, bc_lo, bc_hi));
     return hipGetLastError();
 }
 
-hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int ny,
-                        int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int px,
+                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(get_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, fout, nx, ny, nz, parity, bc_lo, bc_hi));
+                                              s, f, qs, fout, nx, px, ny, nz, parity, bc_lo, bc_hi));
     return hipGetLastError();
 }
 

@@ -1,23 +1,26 @@
 // mlp_train.hip -- training of the learned eddy-viscosity closure on the GPU:
 // forward and backward passes of the 9-64-64-1 network with BF16 operands on
 // the matrix cores (FP32 accumulation), a deterministic reduction of the
-// per-wavefront gradients, and Adam on FP32 master weights.
+// gradient, and Adam on FP32 master weights.
 //
 // Loss (the closure's design, identical in the FP64 oracle):
 //   L = (1/n) sum_s (softplus(o_s) - y_s / scale)^2,
 //   o = w3 . gelu(W2 gelu(W1 z + b1) + b2) + b3,  z = (x - mean) / std,
-// gelu the tanh form (evaluated exactly here; only inference uses the
+// gelu the tanh form (evaluated here through one FP32 sigmoid per
+// activation, which also gives its derivative; only inference uses the FP16
 // polynomial).  Flat parameter order: W1[64][9], b1[64], W2[64][64], b2[64],
 // w3[64], b3.
 //
-// One wavefront handles 64 samples as four 16-sample tiles ct.  Activations
-// are transposed (units x samples) as in inference, so the layer-1 output tile
-// is the B operand of layer 2 and the layer-2 gradient tile is the B operand
-// of the backward product W2^T g2 (A fragments of W2^T packed with the same k
-// permutation).  The weight gradients contract over samples: h1, g2, g1 and z
-// are staged in LDS as [unit][sample] so that 8 consecutive samples are one
-// 16-byte MFMA operand.  Because inputs 9 and 10 of layer 1 are the constant
-// 1 carrying b1, the dW1 product also yields db1.
+// A wavefront handles 64 samples at a time as four 16-sample tiles ct, and
+// walks many such chunks.  Activations are transposed (units x samples) as in
+// inference, so the layer-1 output tile is the B operand of layer 2 and the
+// layer-2 gradient tile is the B operand of the backward product W2^T g2 (A
+// fragments of W2^T packed with the same k permutation).  The weight
+// gradients contract over samples: h1, g2, g1 and z are staged in LDS as
+// [unit][sample] so that 8 consecutive samples are one 16-byte MFMA operand,
+// and the products accumulate across the wavefront's chunks in the matrix
+// accumulators.  Because inputs 9 and 10 of layer 1 are the constant 1
+// carrying b1, the dW1 product also yields db1.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -45,16 +48,16 @@ struct TrainFrag {
     float inv_scale;
 };
 
-__device__ __forceinline__ float gelu_exact(float x) {
+// GELU (tanh form) through one sigmoid: 0.5 (1 + tanh a) = sig(2a),
+// 2a = 2 sqrt(2/pi) (x + 0.044715 x^3); gelu = x sig, and its derivative
+// gelu' = sig + x sig (1 - sig) d(2a)/dx with d(2a)/dx = 2 sqrt(2/pi)
+// (1 + 3 0.044715 x^2).
+__device__ __forceinline__ float gelu_sig(float x) {
     const float a2 = 1.5957691216057308f * x * (1.0f + 0.044715f * x * x);
-    return x / (1.0f + __expf(-a2));
+    return 1.0f / (1.0f + __expf(-a2));
 }
-
-__device__ __forceinline__ float gelu_grad(float x) {
-    const float k = 0.7978845608028654f;
-    const float a = k * (x + 0.044715f * x * x * x);
-    const float t = tanhf(a);
-    return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * k * (1.0f + 3.0f * 0.044715f * x * x);
+__device__ __forceinline__ float gelu_grad_sig(float x, float sg) {
+    return sg + x * sg * (1.0f - sg) * 1.5957691216057308f * (1.0f + 0.134145f * x * x);
 }
 
 __device__ __forceinline__ float softplus_f(float x) {
@@ -71,163 +74,220 @@ __device__ __forceinline__ float wave_sum16(float v) {  // sum over the 16 colum
     return v;
 }
 
-// One wavefront (block of 64 threads) per 64 samples: per-wave partial
-// gradient [NP] and loss sum written to part[blockIdx.x][NPL].
-__global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainFrag *__restrict__ F,
-                                                      const float *__restrict__ X,
-                                                      const float *__restrict__ Y, int n,
-                                                      float inv_n, float *__restrict__ part) {
-    __shared__ __attribute__((aligned(16))) short zs[64 * 16];   // [sample][k]
-    __shared__ __attribute__((aligned(16))) short zT[16 * 64];   // [k][sample]
-    __shared__ __attribute__((aligned(16))) short h1T[64 * 64];  // [unit][sample]
-    __shared__ __attribute__((aligned(16))) short g2T[64 * 64];
-    __shared__ __attribute__((aligned(16))) short g1T[64 * 64];
-    const int lane = threadIdx.x, h = lane >> 4, col = lane & 15;
-    const int s0 = blockIdx.x * 64;
-    float *out = part + (long long)blockIdx.x * NPL;
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    // ---- inputs: this lane's sample ------------------------------------------
-    {
-        const int s = s0 + lane;
-        short z[16];
-        for (int c = 0; c < 9; ++c) {
-            const float x = s < n ? X[(long long)s * 9 + c] : 0.0f;
-            z[c] = bf16s((x - F->mean[c]) * F->istd[c]);
-        }
-        z[9] = z[10] = bf16s(1.0f);
-        for (int c = 11; c < 16; ++c) z[c] = 0;
-        for (int c = 0; c < 16; ++c) {
-            zs[lane * 16 + c] = z[c];
-            zT[c * 64 + lane] = z[c];
-        }
-    }
-    __syncthreads();
+// per-wavefront staging of one 64-sample chunk, [unit or k][sample] in BF16
+struct GradLds {
+    short zs[64 * 16];   // [sample][k]
+    short zT[16 * 64];   // [k][sample]
+    short h1T[64 * 64];  // [unit][sample]
+    short g2T[64 * 64];
+    short g1T[64 * 64];
+};
+constexpr int kGradWaves = 4;          // wavefronts per block
+constexpr int kGradBlocksMax = 256;    // one block per CU (LDS: 4 x 28 KiB)
+static_assert(sizeof(GradLds) * kGradWaves >= sizeof(float) * kGradWaves * NPL,
+              "the block reduction reuses the staging area");
 
-    // per-lane accumulators (units 16u + 4h + r of this lane's quarter)
-    float dw3[16], db2[16];
-    for (int i = 0; i < 16; ++i) dw3[i] = db2[i] = 0.0f;
-    float loss = 0.0f, db3 = 0.0f;
-
-    for (int ct = 0; ct < 4; ++ct) {
-        const int s = s0 + 16 * ct + col;  // this lane's sample (column) in the tile
-        const float m = s < n ? 1.0f : 0.0f;
-        const float yt = s < n ? Y[s] * F->inv_scale : 0.0f;
-        const short4v zb = *reinterpret_cast<const short4v *>(zs + (16 * ct + col) * 16 + 4 * h);
-        floatx4 a1[4];
-        bf16x8 x2[2];
-        for (int u = 0; u < 4; ++u) {
-            const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-            a1[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F->w1f[u][lane], zb, zero, 0, 0, 0);
-            for (int r = 0; r < 4; ++r) {
-                const short hb = bf16s(gelu_exact(a1[u][r]));
-                x2[u >> 1][(u & 1) * 4 + r] = __builtin_bit_cast(__bf16, hb);
-                h1T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] = hb;
-            }
-        }
-        floatx4 a2[4];
-        float part_o = 0.0f;
-        for (int u = 0; u < 4; ++u) {
-            a2[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2f[u][0][lane], x2[0], F->b2f[u][h], 0, 0, 0);
-            a2[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2f[u][1][lane], x2[1], a2[u], 0, 0, 0);
-            for (int r = 0; r < 4; ++r) part_o += F->w3f[u][h][r] * gelu_exact(a2[u][r]);
-        }
-        part_o += __shfl_xor(part_o, 16, 64);
-        part_o += __shfl_xor(part_o, 32, 64);
-        const float o = part_o + F->b3;
-        const float e = softplus_f(o) - yt;
-        const float go = m * 2.0f * e * inv_n / (1.0f + __expf(-o));  // dL/do
-        if (h == 0) {
-            loss += m * e * e;
-            db3 += go;
-        }
-        // layer-2 gradient g2 = go * w3 * gelu'(a2), in the output layout
-        bf16x8 g2b[2];
-        for (int u = 0; u < 4; ++u)
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * u + r;
-                dw3[i] += go * gelu_exact(a2[u][r]);
-                const float g2 = go * F->w3f[u][h][r] * gelu_grad(a2[u][r]);
-                db2[i] += g2;
-                const short gb = bf16s(g2);
-                g2b[u >> 1][(u & 1) * 4 + r] = __builtin_bit_cast(__bf16, gb);
-                g2T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] = gb;
-            }
-        // layer-1 gradient g1 = (W2^T g2) * gelu'(a1)
-        for (int u = 0; u < 4; ++u) {
-            const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-            floatx4 b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2tf[u][0][lane], g2b[0], zero, 0, 0, 0);
-            b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2tf[u][1][lane], g2b[1], b, 0, 0, 0);
-            for (int r = 0; r < 4; ++r)
-                g1T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] = bf16s(b[r] * gelu_grad(a1[u][r]));
-        }
-    }
-    __syncthreads();
-
-    // ---- weight gradients: contractions over the 64 samples on MFMA ---------
+// Gradient of the loss over n samples.  Each wavefront walks the 64-sample
+// chunks c = wave id, wave id + waves in grid, ... in order and keeps its
+// weight-gradient sums in the matrix-core accumulators (dW2, dW1) and in
+// registers (dw3, db2, db3, loss) across chunks; the four wavefronts of a
+// block are then summed in LDS in wave order and the block writes one
+// partial part[blockIdx.x][NPL] (parameters in flat order, then the loss
+// sum).  The chunk assignment and every summation order are fixed, so the
+// result is deterministic.
+__global__ __launch_bounds__(256) void mlp_grad_kernel(const TrainFrag *__restrict__ F,
+                                                       const float *__restrict__ X,
+                                                       const float *__restrict__ Y, int n,
+                                                       float inv_n, float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) GradLds lds[kGradWaves];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, h = lane >> 4, col = lane & 15;
+    GradLds &L = lds[wave];
+    const int nch = (n + 63) / 64;
     typedef short short8v __attribute__((ext_vector_type(8)));
     auto frag8 = [&](const short *base, int row, int ks) -> bf16x8 {
         return __builtin_bit_cast(bf16x8,
                                   *reinterpret_cast<const short8v *>(base + row * 64 + 32 * ks + 8 * h));
     };
-    // dW2[u2][u1] = sum_s g2[u2,s] h1[u1,s]
-    for (int ut2 = 0; ut2 < 4; ++ut2)
-        for (int ut1 = 0; ut1 < 4; ++ut1) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int ks = 0; ks < 2; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(g2T, 16 * ut2 + col, ks),
-                                                              frag8(h1T, 16 * ut1 + col, ks), acc, 0, 0, 0);
-            for (int r = 0; r < 4; ++r)
-                out[P_W2 + (16 * ut2 + 4 * h + r) * 64 + 16 * ut1 + col] = acc[r];
+
+    floatx4 dW2[16], dW1[4];
+    #pragma unroll
+    for (int i = 0; i < 16; ++i) dW2[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+    for (int i = 0; i < 4; ++i) dW1[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float dw3[16], db2[16];
+    #pragma unroll
+    for (int i = 0; i < 16; ++i) dw3[i] = db2[i] = 0.0f;
+    float loss = 0.0f, db3 = 0.0f;
+
+    for (int c = blockIdx.x * kGradWaves + wave; c < nch; c += gridDim.x * kGradWaves) {
+        const int s0 = c * 64;
+        wave_lds_fence();  // the previous chunk's reads of the staging area are done
+        {
+            const int s = s0 + lane;
+            short z[16];
+            #pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float x = s < n ? X[(long long)s * 9 + k] : 0.0f;
+                z[k] = bf16s((x - F->mean[k]) * F->istd[k]);
+            }
+            z[9] = z[10] = bf16s(1.0f);
+            #pragma unroll
+            for (int k = 11; k < 16; ++k) z[k] = 0;
+            #pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                L.zs[lane * 16 + k] = z[k];
+                L.zT[k * 64 + lane] = z[k];
+            }
         }
-    // dW1[u1][k] = sum_s g1[u1,s] z[k,s]; column k = 9 is db1
-    for (int ut1 = 0; ut1 < 4; ++ut1) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int ks = 0; ks < 2; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(g1T, 16 * ut1 + col, ks),
-                                                          frag8(zT, col, ks), acc, 0, 0, 0);
+        wave_lds_fence();
+        for (int ct = 0; ct < 4; ++ct) {
+            const int s = s0 + 16 * ct + col;  // this lane's sample (column) in the tile
+            const float m = s < n ? 1.0f : 0.0f;
+            const float yt = s < n ? Y[s] * F->inv_scale : 0.0f;
+            const short4v zb = *reinterpret_cast<const short4v *>(L.zs + (16 * ct + col) * 16 + 4 * h);
+            floatx4 a1[4], sg1[4];
+            bf16x8 x2[2];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+                a1[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F->w1f[u][lane], zb, zero, 0, 0, 0);
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    sg1[u][r] = gelu_sig(a1[u][r]);
+                    const short hb = bf16s(a1[u][r] * sg1[u][r]);
+                    x2[u >> 1][(u & 1) * 4 + r] = __builtin_bit_cast(__bf16, hb);
+                    L.h1T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] = hb;
+                }
+            }
+            floatx4 a2[4], sg2[4];
+            float part_o = 0.0f;
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a2[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2f[u][0][lane], x2[0], F->b2f[u][h], 0, 0, 0);
+                a2[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2f[u][1][lane], x2[1], a2[u], 0, 0, 0);
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    sg2[u][r] = gelu_sig(a2[u][r]);
+                    part_o += F->w3f[u][h][r] * (a2[u][r] * sg2[u][r]);
+                }
+            }
+            part_o += __shfl_xor(part_o, 16, 64);
+            part_o += __shfl_xor(part_o, 32, 64);
+            const float o = part_o + F->b3;
+            const float e = softplus_f(o) - yt;
+            const float go = m * 2.0f * e * inv_n / (1.0f + __expf(-o));  // dL/do
+            if (h == 0) {
+                loss += m * e * e;
+                db3 += go;
+            }
+            // layer-2 gradient g2 = go * w3 * gelu'(a2), in the output layout
+            bf16x8 g2b[2];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u)
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * u + r;
+                    dw3[i] += go * (a2[u][r] * sg2[u][r]);
+                    const float g2 = go * F->w3f[u][h][r] * gelu_grad_sig(a2[u][r], sg2[u][r]);
+                    db2[i] += g2;
+                    const short gb = bf16s(g2);
+                    g2b[u >> 1][(u & 1) * 4 + r] = __builtin_bit_cast(__bf16, gb);
+                    L.g2T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] = gb;
+                }
+            // layer-1 gradient g1 = (W2^T g2) * gelu'(a1)
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+                floatx4 b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2tf[u][0][lane], g2b[0], zero, 0, 0, 0);
+                b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F->w2tf[u][1][lane], g2b[1], b, 0, 0, 0);
+                #pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    L.g1T[(16 * u + 4 * h + r) * 64 + 16 * ct + col] =
+                        bf16s(b[r] * gelu_grad_sig(a1[u][r], sg1[u][r]));
+            }
+        }
+        wave_lds_fence();
+        // weight gradients: contractions over the chunk's 64 samples, added to
+        // the accumulators.  dW2[u2][u1] = sum_s g2[u2,s] h1[u1,s];
+        // dW1[u1][k] = sum_s g1[u1,s] z[k,s] (column k = 9 is db1)
+        #pragma unroll
+        for (int ut2 = 0; ut2 < 4; ++ut2)
+            #pragma unroll
+            for (int ut1 = 0; ut1 < 4; ++ut1)
+                #pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+                    dW2[4 * ut2 + ut1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        frag8(L.g2T, 16 * ut2 + col, ks), frag8(L.h1T, 16 * ut1 + col, ks),
+                        dW2[4 * ut2 + ut1], 0, 0, 0);
+        #pragma unroll
+        for (int ut1 = 0; ut1 < 4; ++ut1)
+            #pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                dW1[ut1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    frag8(L.g1T, 16 * ut1 + col, ks), frag8(L.zT, col, ks), dW1[ut1], 0, 0, 0);
+    }
+
+    // ---- the wave's sums into LDS (flat parameter order), then the block's
+    __syncthreads();  // every wave is done with its staging area
+    float *st = reinterpret_cast<float *>(&lds[0]) + wave * NPL;
+    #pragma unroll
+    for (int ut2 = 0; ut2 < 4; ++ut2)
+        #pragma unroll
+        for (int ut1 = 0; ut1 < 4; ++ut1)
+            #pragma unroll
+            for (int r = 0; r < 4; ++r)
+                st[P_W2 + (16 * ut2 + 4 * h + r) * 64 + 16 * ut1 + col] = dW2[4 * ut2 + ut1][r];
+    #pragma unroll
+    for (int ut1 = 0; ut1 < 4; ++ut1)
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int u1 = 16 * ut1 + 4 * h + r;
-            if (col < 9) out[P_W1 + u1 * 9 + col] = acc[r];
-            if (col == 9) out[P_B1 + u1] = acc[r];
+            if (col < 9) st[P_W1 + u1 * 9 + col] = dW1[ut1][r];
+            if (col == 9) st[P_B1 + u1] = dW1[ut1][r];
         }
-    }
-    // dw3, db2: sum over the 16 columns of each quarter
+    #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const float a = wave_sum16(dw3[i]);
         const float b = wave_sum16(db2[i]);
         const int u = 16 * (i >> 2) + 4 * h + (i & 3);
         if (col == 0) {
-            out[P_W3 + u] = a;
-            out[P_B2 + u] = b;
+            st[P_W3 + u] = a;
+            st[P_B2 + u] = b;
         }
     }
     const float lsum = wave_sum16(loss);
     const float b3sum = wave_sum16(db3);
     if (lane == 0) {
-        out[P_B3] = b3sum;
-        out[NP] = lsum;
+        st[P_B3] = b3sum;
+        st[NP] = lsum;
     }
+    __syncthreads();
+    const float *s0p = reinterpret_cast<const float *>(&lds[0]);
+    float *out = part + (long long)blockIdx.x * NPL;
+    #pragma unroll
+    for (int i = tid; i < NPL; i += 256)
+        out[i] = ((s0p[i] + s0p[NPL + i]) + s0p[2 * NPL + i]) + s0p[3 * NPL + i];
 }
 
-// grad[i] = sum over waves of part[w][i], fixed order, FP64 accumulation
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *__restrict__ part, int nw,
-                                                         float *__restrict__ grad) {
+// grad[i] = sum over blocks of part[b][i] (fixed order, FP64), then with
+// update != 0 one Adam step on the FP32 master parameter i
+__global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(
+    const float *__restrict__ part, int nb, float *__restrict__ grad, int update,
+    float *__restrict__ p, float *__restrict__ m, float *__restrict__ v, float lr, float b1,
+    float b2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPL) return;
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += part[(long long)w * NPL + i];
-    grad[i] = (float)s;
-}
-
-// Adam on the FP32 master parameters
-__global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ p, float *__restrict__ m,
-                                                       float *__restrict__ v,
-                                                       const float *__restrict__ g, float lr,
-                                                       float b1, float b2, float eps, float c1,
-                                                       float c2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NP) return;
-    const float gi = g[i];
+    for (int b = 0; b < nb; ++b) s += part[(long long)b * NPL + i];
+    const float gi = (float)s;
+    grad[i] = gi;
+    if (!update || i >= NP) return;
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
@@ -299,6 +359,14 @@ lbm_status tfail(lbm_trainer *tr, lbm_status s, const std::string &m) {
             return tfail(tr, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// gradient blocks for n samples: one 64-sample chunk per wavefront while
+// they last, at most one block per CU's worth of the device
+int grad_blocks(int64_t n) {
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t b = (chunks + kGradWaves - 1) / kGradWaves;
+    return (int)(b < kGradBlocksMax ? (b > 0 ? b : 1) : kGradBlocksMax);
+}
+
 lbm_status repack(lbm_trainer *tr) {
     constexpr int total = 4 * 64 * 4 + 4 * 2 * 64 * 8 + 64 + 1;
     hipLaunchKernelGGL(mlp_pack_kernel, dim3((total + 255) / 256), dim3(256), 0, tr->stream, tr->p,
@@ -323,7 +391,7 @@ lbm_status lbm_train_create(const lbm_train_params *prm, const float *params, lb
     tr->prm = *prm;
     tr->stream = static_cast<hipStream_t>(prm->stream);
     tr->max_batch = prm->max_batch;
-    const int nw = (prm->max_batch + 63) / 64;
+    const int nw = grad_blocks(prm->max_batch);
     const size_t a = 256;
     auto up = [&](size_t x) { return (x + a - 1) / a * a; };
     const size_t o_p = 0, o_m = o_p + up(NP * 4), o_v = o_m + up(NP * 4), o_g = o_v + up(NP * 4),
@@ -367,21 +435,21 @@ lbm_status lbm_train_step(lbm_trainer *tr, const float *X, const float *Y, int64
     if (!tr) return LBM_EINVAL;
     if (!X || !Y || n < 1 || n > tr->max_batch)
         return tfail(tr, LBM_EINVAL, "lbm_train_step: need device X, y and 1 <= n <= max_batch");
-    const int nw = (int)((n + 63) / 64);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(nw), dim3(64), 0, tr->stream, tr->frag, X, Y, (int)n,
+    const int nb = grad_blocks(n);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(256), 0, tr->stream, tr->frag, X, Y, (int)n,
                        1.0f / (float)n, tr->part);
     TCHK(tr, hipGetLastError(), "lbm_train_step: gradient");
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NPL + 255) / 256), dim3(256), 0, tr->stream,
-                       tr->part, nw, tr->grad);
-    TCHK(tr, hipGetLastError(), "lbm_train_step: reduce");
+    float c1 = 1.0f, c2 = 1.0f;
     if (update) {
         tr->t += 1;
-        const float c1 = 1.0f - std::pow(tr->prm.beta1, (float)tr->t);
-        const float c2 = 1.0f - std::pow(tr->prm.beta2, (float)tr->t);
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, tr->stream, tr->p,
-                           tr->m, tr->v, tr->grad, tr->prm.lr, tr->prm.beta1, tr->prm.beta2,
-                           tr->prm.eps, c1, c2);
-        TCHK(tr, hipGetLastError(), "lbm_train_step: adam");
+        c1 = 1.0f - std::pow(tr->prm.beta1, (float)tr->t);
+        c2 = 1.0f - std::pow(tr->prm.beta2, (float)tr->t);
+    }
+    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((NPL + 255) / 256), dim3(256), 0, tr->stream,
+                       tr->part, nb, tr->grad, (int)(update != 0), tr->p, tr->m, tr->v,
+                       tr->prm.lr, tr->prm.beta1, tr->prm.beta2, tr->prm.eps, c1, c2);
+    TCHK(tr, hipGetLastError(), "lbm_train_step: reduce");
+    if (update) {
         lbm_status s = repack(tr);
         if (s != LBM_OK) return s;
     }

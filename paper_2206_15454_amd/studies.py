@@ -128,7 +128,7 @@ def field_errors(a, b):
 # ---------------------------------------------------------------------------
 
 def closure_study(out, fine_steps=40000, snapshots=(20000, 30000, 40000), coarse_steps=20000,
-                  avg_from=10000, n_train=8_000_000, epochs=3, batch=8192, lr=1e-3):
+                  avg_from=10000, n_train=None, epochs=3, batch=8192, lr=1e-3):
     import torch
 
     dev = torch.device("cuda")
@@ -180,6 +180,7 @@ def closure_study(out, fine_steps=40000, snapshots=(20000, 30000, 40000), coarse
     hi = Xtr.max(axis=0).astype(np.float64)
     s = float(ytr.mean()) if ytr.mean() > 0 else 1e-5
     rng = np.random.default_rng(7)
+    n_train = Xtr.shape[0] if n_train is None else min(int(n_train), Xtr.shape[0])
     idx = rng.permutation(Xtr.shape[0])[:n_train]
     Xd = torch.from_numpy(np.ascontiguousarray(Xtr[idx])).to(dev)
     yd = torch.from_numpy(np.ascontiguousarray(ytr[idx])).to(dev)
@@ -267,12 +268,15 @@ def closure_study(out, fine_steps=40000, snapshots=(20000, 30000, 40000), coarse
     A["filtered_fine_profile"] = profiles(prof_ref)["u"].tolist()
     A["u_tau"] = math.sqrt(wc.g[0] * wc.ny)
 
-    # 4. throughput of both forms at 1024x256x512
+    # 4. throughput of both forms at 1024x256x512 (the network with its input
+    # ranges opened: on this workload's physics the trained ranges would make
+    # most wavefronts fall back and skip it)
     w5 = inputs.C5
     rho, u = inputs.init_fields_torch(w5, dev)
-    for name, (st, b) in {"f32_smag": ("f32", None), "bf16s_mlp": ("bf16s", blob),
-                          "bf16s_smag": ("bf16s", None), "f16s_mlp": ("f16s", blob),
-                          "bf16sr_smag": ("bf16sr", None)}.items():
+    net = closure.everywhere(blob)
+    for name, (st, b) in {"f32_smag": ("f32", None), "bf16s_mlp": ("bf16s", net),
+                          "bf16sr_mlp": ("bf16sr", net), "bf16s_smag": ("bf16s", None),
+                          "f16s_mlp": ("f16s", net), "bf16sr_smag": ("bf16sr", None)}.items():
         sim = make(w5, st, rho, u, b)
         sim.step(20)
         ms = timed_steps(sim, 200, torch, 200)

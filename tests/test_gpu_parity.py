@@ -212,6 +212,34 @@ def test_streaming_cache_policy_changes_nothing(monkeypatch, storage, nx):
     np.testing.assert_array_equal(res[1], res[0])
 
 
+@pytest.mark.parametrize("storage,nx", [("f32", 70), ("bf16sr", 67), ("f16s", 100), ("f64", 35)])
+def test_row_pitch_changes_nothing(monkeypatch, storage, nx):
+    """Population rows padded to whole 128-byte lines (the default when a row
+    is not; LBMX_PITCH=0 keeps them dense) give bit-identical populations,
+    moments and diagnostics, both AA parities, walls included; with the
+    learned closure too."""
+    from paper_2206_15454_amd import closure
+
+    w = inputs.scaled(inputs.C1, nx, 9, 6, canopy_rows=4)
+    blob = closure.timing_blob(10.0)
+    res = []
+    for pitch in ("0", "1"):
+        monkeypatch.setenv("LBMX_PITCH", pitch)
+        out = []
+        for learned in (False, True):
+            _, g = make_pair(w, storage=storage, seed=10)
+            if learned:
+                g.set_closure(blob)
+            g.step(7)
+            r, u, nt, d = g.moments()
+            out.append((g.get_f(), r, u, nt, d["mass"], d["mlp_fallback"]))
+            g.close()
+        res.append(out)
+    for a, b in zip(res[0], res[1]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16sr"])
 def test_tile_order_changes_nothing(monkeypatch, storage):
     """Row-major and memory-order tile numbering (LBMX_TILE_ORDER forces
