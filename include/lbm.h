@@ -125,15 +125,20 @@ size_t lbm_required_bytes(const lbm_params *p);
  *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1)
  *   LBMX_WIDE=0|1           64-bit population addresses (default: only when
  *                           buffer resources cannot address the array)
- *   LBMX_STREAMING=0|1      non-temporal population accesses (default: when a
- *                           row is a whole number of 128-byte lines)
+ *   LBMX_STREAMING=0|1      non-temporal population accesses (default: when
+ *                           the population array exceeds 256 MiB and a row
+ *                           is a whole number of 128-byte lines)
  *   LBMX_TILE_ORDER=0|1     row-major or memory-order tile numbering (default:
  *                           memory order unless rows stream and a plane is at
  *                           most 96 MiB)
+ *   LBMX_FX=0|1             kernels that leave out the y and z force terms
+ *                           when g_y = g_z = 0 and the drag is x-only
+ *                           (default 1)
  *   LBMX_PITCH=0|1          population rows padded to whole 128-byte lines
- *                           (default 1: rows of nx cells that are not whole
- *                           lines get a pitch of the next whole number of
- *                           lines; the pad cells are never touched) */
+ *                           (default: for population arrays above 256 MiB,
+ *                           rows of nx cells that are not whole lines get a
+ *                           pitch of the next whole number of lines; the pad
+ *                           cells are never touched) */
 lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out);
 
 /* Release the context (and its device memory if the library allocated it). */

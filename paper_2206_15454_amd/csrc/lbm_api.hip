@@ -34,6 +34,7 @@ struct lbm_ctx {
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;
     bool force_wide = false;  // 64-bit population addresses even for small planes
+    bool fx = true;           // the x-only-force kernels when the force is along x (VAR_FX)
     bool streaming = false;   // non-temporal accesses on aligned rows (FLAG_STREAMING)
     bool memorder = false;    // tiles in memory order (FLAG_MEMORDER)
     // device memory
@@ -68,7 +69,7 @@ struct lbm_ctx {
     int64_t evals = 0;       // evaluations so far (fallback counter slot = evals & 1)
     int last_fb_slot = 0;    // slot of the last evaluation
     MlpConst mc{};           // learned closure scalars (kernel arguments)
-    int mlp_grid[4] = {0, 0, 0, 0};  // persistent grid of the learned-closure kernel per variant
+    int mlp_grid[8] = {};    // persistent grid of the learned-closure kernel per variant
     bool diag_fresh = false; // dg holds the diagnostics of the moments lbm_moments reads
     std::string err;
 };
@@ -158,18 +159,35 @@ long long plane_stride(long long n, size_t elt) {
     return qs;
 }
 
-// Population row pitch: rows padded to whole 128-byte lines, so that every
-// row starts on a line and the row-aligned accesses can stream (rows of 350
-// FP32 cells, 1 400 B, otherwise share their end lines with the next row).
-// The padding cells are never read or written.  No padding when a row is
-// already whole lines or the padded array would not be indexable in 32 bits;
-// LBMX_PITCH=0 disables it (the populations are bit-identical either way).
+// Whether the population accesses stream (non-temporal) by default: only for
+// population arrays larger than the 256 MiB Infinity Cache.  Smaller arrays
+// keep lines there from one step to the next with the default policy;
+// streaming them was measured slower (200x80x160 FP32, 195 MB: 32.6k against
+// 41.5k MLUPS; 250x100x200 BF16SR, 190 MB: 61.2k against 74.1k), larger ones
+// faster (250x100x200 FP32, 380 MB: 34.5k against 32.7k; 350x140x280
+// BF16SR, 522 MB: 60.0k against 56.4k; 512x128x256 BF16S, 637 MB: 72.0k
+// against 61.3k).
+constexpr long long kStreamMinBytes = 256LL << 20;
+
+bool large_array(const lbm_params *p) {
+    const long long elt = (long long)storage_bytes(p->storage);
+    return (long long)NQ * p->nx * p->ny * p->nz * elt > kStreamMinBytes;
+}
+
+// Population row pitch: for the arrays that stream, rows padded to whole
+// 128-byte lines, so that every row starts on a line and the row-aligned
+// accesses can stream (rows of 350 FP32 cells, 1 400 B, otherwise share
+// their end lines with the next row).  The padding cells are never read or
+// written.  No padding when a row is already whole lines, for arrays that do
+// not stream, or when the padded array would not be indexable in 32 bits.
+// LBMX_PITCH=0|1 forces dense rows or padded rows (the populations are
+// bit-identical either way).
 int row_pitch(const lbm_params *p) {
     const long long elt = (long long)storage_bytes(p->storage);
     const long long per_line = 128 / elt;
-    long long px = (p->nx + per_line - 1) / per_line * per_line;
-    if (const char *e = std::getenv("LBMX_PITCH"))
-        if (std::atoi(e) == 0) px = p->nx;
+    bool pad = large_array(p);
+    if (const char *e = std::getenv("LBMX_PITCH")) pad = std::atoi(e) != 0;
+    long long px = pad ? (p->nx + per_line - 1) / per_line * per_line : p->nx;
     if (px * p->ny * p->nz >= (1LL << 31)) px = p->nx;
     return (int)px;
 }
@@ -272,9 +290,11 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->ntiles = c->tpp * p->ny;
     if (const char *e = std::getenv("LBMX_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     if (const char *e = std::getenv("LBMX_WIDE")) c->force_wide = std::atoi(e) != 0;
-    // streaming (non-temporal) accesses where rows are whole 128-byte lines
-    // (the planes start on 256-byte boundaries); LBMX_STREAMING=0/1 overrides
-    c->streaming = ((long long)c->px * (long long)c->elt) % 128 == 0;
+    if (const char *e = std::getenv("LBMX_FX")) c->fx = std::atoi(e) != 0;
+    // streaming (non-temporal) accesses for arrays beyond the Infinity Cache
+    // whose rows are whole 128-byte lines (the planes start on 256-byte
+    // boundaries); LBMX_STREAMING=0/1 overrides
+    c->streaming = large_array(p) && ((long long)c->px * (long long)c->elt) % 128 == 0;
     if (const char *e = std::getenv("LBMX_STREAMING")) c->streaming = std::atoi(e) != 0;
     // tile order: the tiles that run at the same time span the fewest pages in
     // memory order.  The row-major order measured faster only for streaming
@@ -502,7 +522,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.mc = c->mc;
     int base_flags = FLAG_IMPULSE;
     if (c->vector_drag) base_flags |= FLAG_VECTOR_DRAG;
-    if (c->p.g[1] == 0.0 && c->p.g[2] == 0.0 && !c->vector_drag) base_flags |= FLAG_IMPULSE_X;
+    if (c->p.g[1] == 0.0 && c->p.g[2] == 0.0 && !c->vector_drag) {
+        base_flags |= FLAG_IMPULSE_X;
+        if (c->fx) base_flags |= FLAG_FX;
+    }
     if (c->xcd_remap) base_flags |= FLAG_XCD_REMAP;
     if (c->forest) base_flags |= FLAG_FOREST;
     if (c->streaming) base_flags |= FLAG_STREAMING;
@@ -536,7 +559,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         if (evaluate) {
             // the persistent grid depends on the kernel variant only: the
             // occupancy query runs once per variant and context
-            const int v = ((a.flags & FLAG_FOREST) ? 1 : 0) | ((a.flags & FLAG_WIDE) ? 2 : 0);
+            const int v = ((a.flags & FLAG_FOREST) ? 1 : 0) | ((a.flags & FLAG_WIDE) ? 2 : 0) |
+                          ((a.flags & FLAG_FX) ? 4 : 0);
             if (c->mlp_grid[v] == 0)
                 e = mlp_launch_grid(c->p.storage, a.flags, c->ntiles, &c->mlp_grid[v]);
             if (e == hipSuccess)

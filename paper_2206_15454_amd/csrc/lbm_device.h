@@ -49,7 +49,8 @@ enum : int {
     FLAG_WIDE = 512,       // the population array has 2^32 bytes or more
     FLAG_IMPULSE_X = 1024, // g_y = g_z = 0 and x-only drag: the y, z forces are 0
     FLAG_STREAMING = 2048, // rows start on cache lines: aligned accesses are non-temporal
-    FLAG_MEMORDER = 4096   // tiles numbered in memory order (rows not streaming, or planes above 96 MiB)
+    FLAG_MEMORDER = 4096,  // tiles numbered in memory order (rows not streaming, or planes above 96 MiB)
+    FLAG_FX = 8192         // driving force and drag along x only: F_y = F_z = 0 (VAR_FX)
 };
 
 // Compile-time variants of the step (a bit set; chosen at launch from the flags)
@@ -57,7 +58,8 @@ enum : int {
     VAR_FOREST = 1,        // FLAG_FOREST
     VAR_NUT_IN = 2,        // FLAG_NUT_IN
     VAR_WIDE = 4,          // FLAG_WIDE: population arrays of 4 GiB or more (64-bit addresses)
-    VAR_STREAM = 8         // FLAG_STREAMING (plain step kernel)
+    VAR_STREAM = 8,        // FLAG_STREAMING (plain step kernel)
+    VAR_FX = 16            // FLAG_FX: the y and z forces are zero at compile time
 };
 
 // Population loads and stores of the auxiliary kernels (plain cached accesses).

@@ -251,17 +251,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C irho = arith_rcp(rho);
 
     // ---- a4: velocity with the driving force, canopy drag, corrected u ----
-    const C gx = sc(a.g[0], a.gf[0]), gy = sc(a.g[1], a.gf[1]), gz = sc(a.g[2], a.gf[2]);
+    // VAR_FX: the driving force and the drag act along x only, so F_y = F_z =
+    // 0 is known here and the terms they enter are left out (the general
+    // form gives the same values: those terms are exact zeros)
+    constexpr bool FX = (VAR & VAR_FX) != 0;
+    const C gx = sc(a.g[0], a.gf[0]);
+    const C gy = FX ? C(0) : sc(a.g[1], a.gf[1]), gz = FX ? C(0) : sc(a.g[2], a.gf[2]);
     C ux = (jx + C(0.5) * rho * gx) * irho;
-    C uy = (jy + C(0.5) * rho * gy) * irho;
-    C uz = (jz + C(0.5) * rho * gz) * irho;
+    C uy = FX ? jy * irho : (jy + C(0.5) * rho * gy) * irho;
+    C uz = FX ? jz * irho : (jz + C(0.5) * rho * gz) * irho;
     C ax = gx, ay = gy, az = gz;  // total acceleration
     auto drag = [&](C lad) {
         const C speed = arith_sqrt(ux * ux + uy * uy + uz * uz);
         const C kd = -sc(a.cd, a.cdf) * lad * speed;  // drag acceleration per unit velocity
         const C adx = kd * ux;
         ax += adx;
-        if (a.flags & FLAG_VECTOR_DRAG) {
+        if (!FX && (a.flags & FLAG_VECTOR_DRAG)) {
             const C ady = kd * uy, adz = kd * uz;
             ay += ady;
             az += adz;
@@ -278,7 +283,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     else
         lad = (C)a.lad[j];
     if (lad > C(0)) drag(lad);
-    const C Fx = rho * ax, Fy = rho * ay, Fz = rho * az;
+    const C Fx = rho * ax, Fy = FX ? C(0) : rho * ay, Fz = FX ? C(0) : rho * az;
 
     // ---- a5: Smagorinsky: Pi_neq = P - drho/3 I - rho u u -----------------
     const C third = C(1) / C(3);
@@ -359,7 +364,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // The weight is folded into the per-cell scalars of its class (1/18 for
     // the axis directions, 1/36 for the edge directions).
     const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
-    const C uF = ux * Fx + uy * Fy + uz * Fz;
+    const C uF = FX ? ux * Fx : ux * Fx + uy * Fy + uz * Fz;
     const C pref = C(1) - C(0.5) * itau;
     const C om = C(1) - itau;
     const C K = itau * (drho - rho * usq15) - C(3) * pref * uF;
@@ -377,10 +382,16 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         constexpr int cls = weight(q) == weight(1) ? 0 : 1;
         C cu = C(-0.0), cF = C(-0.0);
         if (cx) { cu += cx > 0 ? ux : -ux; cF += cx > 0 ? Fx : -Fx; }
-        if (cy) { cu += cy > 0 ? uy : -uy; cF += cy > 0 ? Fy : -Fy; }
-        if (cz) { cu += cz > 0 ? uz : -uz; cF += cz > 0 ? Fz : -Fz; }
-        const C even = Kw[cls] + cu * (a1w[cls] * cu + a2w[cls] * cF);
-        const C odd = b1w[cls] * cu + b2w[cls] * cF;
+        if (cy) { cu += cy > 0 ? uy : -uy; if (!FX) cF += cy > 0 ? Fy : -Fy; }
+        if (cz) { cu += cz > 0 ? uz : -uz; if (!FX) cF += cz > 0 ? Fz : -Fz; }
+        C even, odd;
+        if constexpr (FX && cx == 0) {  // c.F = 0
+            even = Kw[cls] + cu * (a1w[cls] * cu);
+            odd = b1w[cls] * cu;
+        } else {
+            even = Kw[cls] + cu * (a1w[cls] * cu + a2w[cls] * cF);
+            odd = b1w[cls] * cu + b2w[cls] * cF;
+        }
         v[q] = v[q] * om + (even + odd);
         v[q + 1] = v[q + 1] * om + (even - odd);
     });
@@ -855,38 +866,51 @@ __global__ __launch_bounds__(256) void fill_kernel(double *p, double v, size_t n
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
-// compile-time variant from the launch flags
-#define LBMX_VARIANT(flags, CALL)                                      \
-    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
-            ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0) |                 \
-            ((flags) & FLAG_WIDE ? VAR_WIDE : 0) |                     \
-            ((flags) & FLAG_STREAMING ? VAR_STREAM : 0)) {             \
-    case 0: { constexpr int V = 0; CALL; } break;                      \
-    case 1: { constexpr int V = 1; CALL; } break;                      \
-    case 2: { constexpr int V = 2; CALL; } break;                      \
-    case 3: { constexpr int V = 3; CALL; } break;                      \
-    case 4: { constexpr int V = 4; CALL; } break;                      \
-    case 5: { constexpr int V = 5; CALL; } break;                      \
-    case 6: { constexpr int V = 6; CALL; } break;                      \
-    case 7: { constexpr int V = 7; CALL; } break;                      \
-    case 8: { constexpr int V = 8; CALL; } break;                      \
-    case 9: { constexpr int V = 9; CALL; } break;                      \
-    case 10: { constexpr int V = 10; CALL; } break;                    \
-    case 11: { constexpr int V = 11; CALL; } break;                    \
-    case 12: { constexpr int V = 12; CALL; } break;                    \
-    case 13: { constexpr int V = 13; CALL; } break;                    \
-    case 14: { constexpr int V = 14; CALL; } break;                    \
-    default: { constexpr int V = 15; CALL; } break;                    \
+// compile-time variant from the launch flags (VAR_FX only without 64-bit
+// addresses: a launch with both takes the general kernel)
+#define LBMX_VARIANT(flags, CALL)                                                  \
+    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                             \
+            ((flags) & FLAG_NUT_IN ? VAR_NUT_IN : 0) |                             \
+            ((flags) & FLAG_WIDE ? VAR_WIDE : 0) |                                 \
+            ((flags) & FLAG_STREAMING ? VAR_STREAM : 0) |                          \
+            (((flags) & FLAG_FX) && !((flags) & FLAG_WIDE) ? VAR_FX : 0)) {        \
+    case 0: { constexpr int V = 0; CALL; } break;                                  \
+    case 1: { constexpr int V = 1; CALL; } break;                                  \
+    case 2: { constexpr int V = 2; CALL; } break;                                  \
+    case 3: { constexpr int V = 3; CALL; } break;                                  \
+    case 4: { constexpr int V = 4; CALL; } break;                                  \
+    case 5: { constexpr int V = 5; CALL; } break;                                  \
+    case 6: { constexpr int V = 6; CALL; } break;                                  \
+    case 7: { constexpr int V = 7; CALL; } break;                                  \
+    case 8: { constexpr int V = 8; CALL; } break;                                  \
+    case 9: { constexpr int V = 9; CALL; } break;                                  \
+    case 10: { constexpr int V = 10; CALL; } break;                                \
+    case 11: { constexpr int V = 11; CALL; } break;                                \
+    case 12: { constexpr int V = 12; CALL; } break;                                \
+    case 13: { constexpr int V = 13; CALL; } break;                                \
+    case 14: { constexpr int V = 14; CALL; } break;                                \
+    case 15: { constexpr int V = 15; CALL; } break;                                \
+    case VAR_FX | 0: { constexpr int V = VAR_FX | 0; CALL; } break;                \
+    case VAR_FX | 1: { constexpr int V = VAR_FX | 1; CALL; } break;                \
+    case VAR_FX | 2: { constexpr int V = VAR_FX | 2; CALL; } break;                \
+    case VAR_FX | 3: { constexpr int V = VAR_FX | 3; CALL; } break;                \
+    case VAR_FX | 8: { constexpr int V = VAR_FX | 8; CALL; } break;                \
+    case VAR_FX | 9: { constexpr int V = VAR_FX | 9; CALL; } break;                \
+    case VAR_FX | 10: { constexpr int V = VAR_FX | 10; CALL; } break;              \
+    default: { constexpr int V = VAR_FX | 11; CALL; } break;                       \
     }
 
 // the learned-closure kernel's variants (it computes nu_t: never VAR_NUT_IN)
-#define LBMX_VARIANT_MLP(flags, CALL)                                  \
-    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                 \
-            ((flags) & FLAG_WIDE ? VAR_WIDE : 0)) {                    \
-    case 0: { constexpr int V = 0; CALL; } break;                      \
-    case VAR_FOREST: { constexpr int V = VAR_FOREST; CALL; } break;    \
-    case VAR_WIDE: { constexpr int V = VAR_WIDE; CALL; } break;        \
-    default: { constexpr int V = VAR_FOREST | VAR_WIDE; CALL; } break; \
+#define LBMX_VARIANT_MLP(flags, CALL)                                              \
+    switch (((flags) & FLAG_FOREST ? VAR_FOREST : 0) |                             \
+            ((flags) & FLAG_WIDE ? VAR_WIDE : 0) |                                 \
+            (((flags) & FLAG_FX) && !((flags) & FLAG_WIDE) ? VAR_FX : 0)) {        \
+    case 0: { constexpr int V = 0; CALL; } break;                                  \
+    case VAR_FOREST: { constexpr int V = VAR_FOREST; CALL; } break;                \
+    case VAR_WIDE: { constexpr int V = VAR_WIDE; CALL; } break;                    \
+    case VAR_FOREST | VAR_WIDE: { constexpr int V = VAR_FOREST | VAR_WIDE; CALL; } break; \
+    case VAR_FX: { constexpr int V = VAR_FX; CALL; } break;                        \
+    default: { constexpr int V = VAR_FX | VAR_FOREST; CALL; } break;               \
     }
 
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {

@@ -240,6 +240,34 @@ def test_row_pitch_changes_nothing(monkeypatch, storage, nx):
             np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
+def test_x_only_force_kernels_change_nothing(monkeypatch, storage):
+    """With the driving force along x and x-only drag (F_y = F_z = 0), the
+    step runs kernels that leave out the y and z force terms (LBMX_FX=0
+    forces the general ones): bit-identical populations and moments, canopy
+    rows and walls included, plain and learned closure."""
+    from paper_2206_15454_amd import closure
+
+    w = inputs.scaled(inputs.C1, 96, 12, 8, canopy_rows=5)
+    blob = closure.timing_blob(10.0)
+    res = []
+    for fx in ("0", "1"):
+        monkeypatch.setenv("LBMX_FX", fx)
+        out = []
+        for learned in (False, True):
+            _, g = make_pair(w, storage=storage, seed=12)
+            if learned:
+                g.set_closure(blob)
+            g.step(9)
+            r, u, nt, d = g.moments()
+            out.append((g.get_f(), r, u, nt, d["mass"], d["imp_x"]))
+            g.close()
+        res.append(out)
+    for a, b in zip(res[0], res[1]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16sr"])
 def test_tile_order_changes_nothing(monkeypatch, storage):
     """Row-major and memory-order tile numbering (LBMX_TILE_ORDER forces
