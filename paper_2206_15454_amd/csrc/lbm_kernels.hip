@@ -293,21 +293,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     const C nxy = pxy - rho * ux * uy;
     const C nxz = pxz - rho * ux * uz;
     const C nyz = pyz - rho * uy * uz;
-    const C Qh = arith_sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
-                      C(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
     const C tau0 = sc(a.tau0, a.tau0f);
     // tau = (tau0 + sqrt(tau0^2 + X))/2, X = 18 sqrt2 C Q^(1/2)/rho, written
     // as tau0 + 3 nu_t with nu_t = X / (6 (sqrt(tau0^2 + X) + tau0))
-    const C X = sc(a.ksmag, a.ksmagf) * Qh * irho;
-    C nut = X * arith_rcp(C(6) * (arith_sqrt(tau0 * tau0 + X) + tau0));
+    auto smagorinsky = [&]() -> C {
+        const C Qh = arith_sqrt(nxx * nxx + nyy * nyy + nzz * nzz +
+                                C(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
+        const C X = sc(a.ksmag, a.ksmagf) * Qh * irho;
+        return X * arith_rcp(C(6) * (arith_sqrt(tau0 * tau0 + X) + tau0));
+    };
     const long long ncell = (long long)nx * ny * nz;
+    C nut;
     if constexpr ((VAR & VAR_NUT_IN) != 0) {
         // the learned closure's nu_t of its last evaluation, reused
         nut = static_cast<const C *>(a.mom)[4 * ncell + self];
-    }
-    if constexpr (LEARNED) {
+    } else if constexpr (!LEARNED) {
+        nut = smagorinsky();
+    } else {
         // learned closure where the features are inside the trained range,
-        // Smagorinsky (above) elsewhere
+        // Smagorinsky elsewhere (evaluated only in a wavefront that has such
+        // a cell: the test is uniform per wavefront)
         const int tid = threadIdx.x + threadIdx.y * blockDim.x;
         const int lane = tid & 63;
         float x[9];
@@ -336,7 +341,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             wave_lds_sync();  // the previous tile's reads of this wave's staging area are done
             mlp_stage_inputs(zst, lane, z);
             wave_lds_sync();
-            const float o = mlp_forward_wave(frag, zst, lane) + mc->b3;
+            const float o = mlp_forward_wave(frag, zst, lane, mc->b3);
             static_for<NQ>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 v[q] = pst[q * 256 + tid];
@@ -347,7 +352,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             learned = mc->scale * mlp_softplus(o);
             use = in_range && __builtin_isfinite(learned);
         }
-        if (use) nut = (C)learned;
+        nut = (C)learned;
+        if (__builtin_amdgcn_ballot_w64(!use) != 0) {
+            const C ns = smagorinsky();
+            if (!use) nut = ns;
+        }
         fallbacks += (!use && active) ? 1u : 0u;
     }
     const C tau = tau0 + C(3) * nut;

@@ -12,8 +12,9 @@
 //            B = [z0..z8, 1, 1, 0..] of 16 cells
 //   layer 2: mfma 16x16x32 f16 (two k steps), A = W2 (FP16) with permuted
 //            k, C initialised with b2 (the inputs are gelu(h1), FP16)
-//   output : o = b3 + w3 . gelu(h2) (FP16 pairs, dot2 into FP32, then a sum
-//            over the four lane quarters of a column)
+//   output : mfma 16x16x32 f16 (two k steps), A = w3 in every row (permuted
+//            k), B = gelu(h2), C initialised with b3: every row of the
+//            result holds o of its column
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +40,7 @@ struct MlpParams {
     short4v w1f[4][64];      // layer-1 A fragments [unit tile][lane]
     half8 w2f[4][2][64];     // layer-2 A fragments (FP16) [unit tile][k step][lane]
     floatx4 b2f[4][4];       // layer-2 bias in output layout [unit tile][lane quarter]
-    half2v w3h[4][4][2];     // output weights (FP16 pairs r = 0,1 and 2,3) [tile][quarter]
+    half8 w3a[2][4];         // output layer A fragments (w3 in every row) [k step][lane quarter]
     unsigned long long fallback[2];  // cells that fell back, per step parity
 };
 
@@ -54,7 +55,7 @@ __host__ __device__ constexpr int mlp_l2_unit_in(int ks, int h, int t) {
 struct MlpFrag {
     short4v w1[4];
     floatx4 b2[4];
-    half2v w3[4][2];
+    half8 w3[2];
     const half8 *w2;  // LDS copy of MlpParams::w2f, [unit tile][k step][lane]
 };
 
@@ -66,9 +67,9 @@ __device__ __forceinline__ MlpFrag mlp_load_frag(const MlpParams *p, int lane,
     for (int u = 0; u < 4; ++u) {
         f.w1[u] = p->w1f[u][lane];
         f.b2[u] = p->b2f[u][h];
-        f.w3[u][0] = p->w3h[u][h][0];
-        f.w3[u][1] = p->w3h[u][h][1];
     }
+    f.w3[0] = p->w3a[0][h];
+    f.w3[1] = p->w3a[1][h];
     f.w2 = w2_lds;
     return f;
 }
@@ -154,14 +155,14 @@ __device__ __forceinline__ void mlp_stage_inputs(short *lds, int lane, const sho
     *reinterpret_cast<short8v *>(lds + lane * 16 + 8) = hi;
 }
 
-// o (pre-softplus output, without b3) for this lane's cell.  Layer 1 runs for
-// the four 16-cell column tiles first (their FP16 activations stay in
-// registers), so that each layer-2 weight fragment is read from LDS once per
-// 64 cells and serves the four column tiles.  Each lane then holds a partial
-// output of its lane quarter for every column tile; two lane swaps across
-// the wave halves and the quarters (v_permlane32_swap, v_permlane16_swap)
-// sum them so that lane quarter h ends with column tile h.
-__device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short *lds, int lane) {
+// o (pre-softplus output) for this lane's cell.  Layer 1 runs for the four
+// 16-cell column tiles first (their FP16 activations stay in registers), so
+// that each layer-2 weight fragment is read from LDS once per 64 cells and
+// serves the four column tiles.  The output layer is a third product on the
+// matrix cores: with w3 in every row of A, every row of a column tile's
+// result holds o of that column, and lane quarter h keeps column tile h.
+__device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short *lds, int lane,
+                                                  float b3) {
     const int h = lane >> 4, col = lane & 15;
     half8 x2[4][2];
 #pragma unroll
@@ -180,31 +181,38 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short 
             x2[ct][u >> 1][o + 3] = g1[1];
         }
     }
-    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    floatx4 acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const half8 wa = f.w2[(2 * u) * 64 + lane], wb = f.w2[(2 * u + 1) * 64 + lane];
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{b3, b3, b3, b3};
+    // layer 2 by pairs of unit tiles (one k step of the output layer each):
+    // both tiles of the pair for a column tile, then the output product
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        half8 w[2][2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            w[p][0] = f.w2[(2 * (2 * ks + p)) * 64 + lane];
+            w[p][1] = f.w2[(2 * (2 * ks + p) + 1) * 64 + lane];
+        }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa, x2[ct][0], f.b2[u], 0, 0, 0);
-            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(wb, x2[ct][1], e, 0, 0, 0);
-            const half2v g0 = mlp_gelu_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
-            const half2v g1 = mlp_gelu_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
-            part[ct] = __builtin_amdgcn_fdot2(g0, f.w3[u][0], part[ct], false);
-            part[ct] = __builtin_amdgcn_fdot2(g1, f.w3[u][1], part[ct], false);
+            half8 x3;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int u = 2 * ks + p;
+                floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[p][0], x2[ct][0], f.b2[u], 0, 0, 0);
+                e = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[p][1], x2[ct][1], e, 0, 0, 0);
+                const half2v g0 = mlp_gelu_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
+                const half2v g1 = mlp_gelu_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
+                x3[4 * p] = g0[0];
+                x3[4 * p + 1] = g0[1];
+                x3[4 * p + 2] = g1[0];
+                x3[4 * p + 3] = g1[1];
+            }
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(f.w3[ks], x3, acc[ct], 0, 0, 0);
         }
     }
-    // halves: lanes 0-31 keep column tiles 0 and 1, lanes 32-63 tiles 2 and 3
-    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
-                                                      __float_as_uint(part[2]), false, false);
-    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[1]),
-                                                      __float_as_uint(part[3]), false, false);
-    const float a02 = __uint_as_float(s02[0]) + __uint_as_float(s02[1]);
-    const float a13 = __uint_as_float(s13[0]) + __uint_as_float(s13[1]);
-    // quarters: the lower 16 lanes of each half keep the even tile, the upper the odd
-    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(a02), __float_as_uint(a13),
-                                                    false, false);
-    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+    return h == 0 ? acc[0][0] : h == 1 ? acc[1][0] : h == 2 ? acc[2][0] : acc[3][0];
 }
 
 }  // namespace lbmx

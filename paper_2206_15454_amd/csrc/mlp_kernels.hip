@@ -118,11 +118,14 @@ bool mlp_pack_blob(const void *blob, size_t nbytes, void *dev, MlpConst *mc, std
                 }
     for (int ut = 0; ut < 4; ++ut)
         for (int hq = 0; hq < 4; ++hq)
-            for (int r = 0; r < 4; ++r) {
-                const int u = 16 * ut + 4 * hq + r;
-                P.b2f[ut][hq][r] = f32_at(b, 184 + 256 + 4 * u);
-                const float wv = from_bf16_bits(u16_at(b, w3o + 2 * u));
-                P.w3h[ut][hq][r / 2][r % 2] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
+            for (int r = 0; r < 4; ++r)
+                P.b2f[ut][hq][r] = f32_at(b, 184 + 256 + 4 * (16 * ut + 4 * hq + r));
+    // output layer: w3 of layer-2 unit mlp_l2_unit_in(ks, hq, t) in every row
+    for (int ks = 0; ks < 2; ++ks)
+        for (int hq = 0; hq < 4; ++hq)
+            for (int t = 0; t < 8; ++t) {
+                const float wv = from_bf16_bits(u16_at(b, w3o + 2 * mlp_l2_unit_in(ks, hq, t)));
+                P.w3a[ks][hq][t] = __builtin_bit_cast(_Float16, to_f16_bits(wv));
             }
     std::memcpy(dev, &P, sizeof(P));
     for (int i = 0; i < kMlpIn; ++i) {
