@@ -283,8 +283,17 @@ __global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(
     float b2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPL) return;
+    // fixed summation order; the loads of a group of 8 are issued together
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(long long)b * NPL + i];
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[(long long)(b + k) * NPL + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; b < nb; ++b) s += part[(long long)b * NPL + i];
     const float gi = (float)s;
     grad[i] = gi;
     if (!update || i >= NP) return;
