@@ -60,6 +60,9 @@ def test_f64_canopy_200_steps_matches_oracle():
     ((40, 6, 5), (1, 3)),     # forced-equilibrium top (the paper's ABL top)
     ((33, 4, 3), (3, 3)),     # forced equilibrium at both ends
     ((20, 1, 4), (2, 3)),     # one row: free slip below, equilibrium above
+    ((1, 5, 1), (1, 2)),      # one column: x and z periodic onto the cell itself
+    ((1, 4, 6), (1, 1)),      # one cell wide in x
+    ((5, 3, 1), (2, 1)),      # one cell deep in z
 ])
 def test_f64_boundaries_and_ragged_grids(shape, bcs):
     nx, ny, nz = shape
@@ -293,6 +296,18 @@ def test_errors_and_state_machine():
     with pytest.raises(lbm.LBMError) as e:
         g.step(1)
     assert e.value.status == 4  # ESTATE before init
+    # zero steps change nothing; a negative count is invalid
+    rho0 = 1.0 + 0.01 * np.arange(g.n).reshape(g.shape) / g.n
+    u0 = np.full((3,) + g.shape, 0.01)
+    g.init(rho0, u0)
+    g.step(0)
+    r, u, nt, d = g.moments()
+    assert d["t"] == 0
+    np.testing.assert_allclose(r, rho0, rtol=1e-6)
+    np.testing.assert_allclose(u, u0, rtol=1e-5)
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(-1)
+    assert e.value.status == 1
     with pytest.raises(lbm.LBMError):
         g.set_canopy(0.2, np.zeros(3))
     with pytest.raises(lbm.LBMError):
