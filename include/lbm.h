@@ -121,7 +121,8 @@ size_t lbm_required_bytes(const lbm_params *p);
  * may differ in their last bits through the summation order):
  *   LBMX_BX=32|64|128|256   tile width in x (default: the widest of 256, 128,
  *                           64 that pads a row least)
- *   LBMX_QPAD=bytes         pad between population planes (default 1024)
+ *   LBMX_QPAD=bytes         pad between population planes (default 2048 for
+ *                           the 16-bit types, 1024 otherwise)
  *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1)
  *   LBMX_WIDE=0|1           64-bit population addresses (default: only when
  *                           buffer resources cannot address the array)

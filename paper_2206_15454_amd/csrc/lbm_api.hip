@@ -146,11 +146,15 @@ void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
 
 // population plane stride: rounded to 256 B plus a pad that staggers the 19
 // plane starts across HBM channels (a power-of-two-aligned stride makes the 19
-// concurrent streams of a wave start in the same channel; 1 KiB measured best)
+// concurrent streams of a wave start in the same channel).  1 KiB for FP32
+// and FP64, 2 KiB for the 16-bit types: measured best over 0.5-4 KiB at
+// 512x128x256 (16-bit: 0.695 -> 0.708 of the roofline with 2 KiB) and no
+// worse at 1024x256x512, 350x140x280 and the forest case; for FP32, 2 KiB
+// was better at 512x128x256 and worse at the other two, FP64 unchanged.
 long long plane_stride(long long n, size_t elt) {
     long long per = (long long)(kAlign / elt);
     long long qs = (n + per - 1) / per * per;
-    long long pad_bytes = 1024;
+    long long pad_bytes = elt == 2 ? 2048 : 1024;
     if (const char *e = std::getenv("LBMX_QPAD")) {
         const long long v = std::atoll(e);
         if (v >= 0 && v <= (1LL << 30)) pad_bytes = v;
