@@ -121,6 +121,9 @@ size_t lbm_required_bytes(const lbm_params *p);
  * may differ in their last bits through the summation order):
  *   LBMX_BX=32|64|128|256   tile width in x (default: the widest of 256, 128,
  *                           64 that pads a row least)
+ *   LBMX_ZALIGN=bytes       population z-layers (px ny cells) rounded up to a
+ *   LBMX_ZPAD=bytes         multiple of, or widened by, this many bytes (a
+ *                           multiple of 128; default: neither)
  *   LBMX_QPAD=bytes         pad between population planes (default 2048 for
  *                           the 16-bit types, 1024 otherwise)
  *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1)

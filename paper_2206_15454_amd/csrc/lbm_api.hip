@@ -30,6 +30,7 @@ struct lbm_ctx {
     size_t celt = 0;     // bytes per arithmetic value
     long long qs = 0;    // population plane stride, elements
     int px = 0;          // population row pitch, cells (>= nx)
+    int zp = 0;          // population z-layer pitch, cells (>= px ny)
     // launch geometry
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;
@@ -124,6 +125,10 @@ bool valid_params(const lbm_params *p, std::string *why) {
 // ragged last tile cost bandwidth: 350 cells in 256-wide tiles leave 32% of
 // the lanes idle, in 128-wide tiles 9%).  32-wide tiles (LBMX_BX=32 only)
 // pad less but were measured slower: their short rows split cache lines.
+// Packing the tails of several rows into one wave (350 cells in 5.5 waves
+// instead of 6) was built and measured: no faster at 350x140x280, slower
+// for FP32 at 200x80x160 (a wave of eight 8-cell tails touches eight
+// lines), and its mapping cost the BF16SR step 2 % on other grids.
 void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
     int BX = 256;
     long long best = -1;
@@ -196,6 +201,27 @@ int row_pitch(const lbm_params *p) {
     return (int)px;
 }
 
+// population z-layer pitch (cells): px ny, or, for tuning, rounded up to a
+// multiple of LBMX_ZALIGN bytes and/or widened by LBMX_ZPAD bytes (multiples
+// of 128, so that rows stay on cache lines).  The padding cells are never
+// read or written.  No padding when the padded array would not be indexable
+// in 32 bits.
+int z_pitch(const lbm_params *p, int px) {
+    const long long elt = (long long)storage_bytes(p->storage);
+    long long bytes = (long long)px * p->ny * elt;
+    if (const char *e = std::getenv("LBMX_ZALIGN")) {
+        const long long v = std::atoll(e);
+        if (v > 0 && v <= (1LL << 30) && v % 128 == 0) bytes = (bytes + v - 1) / v * v;
+    }
+    if (const char *e = std::getenv("LBMX_ZPAD")) {
+        const long long v = std::atoll(e);
+        if (v > 0 && v <= (1LL << 30) && v % 128 == 0) bytes += v;
+    }
+    long long zp = bytes / elt;
+    if (zp * p->nz >= (1LL << 31)) zp = (long long)px * p->ny;
+    return (int)zp;
+}
+
 struct Layout {
     size_t f, mom, lad, imp, dg, stats, red, prof, mlp, fidx, ftab, ftabf, total;
 };
@@ -208,7 +234,7 @@ Layout layout(const lbm_params *p) {
     int bx, bz, nbx, nbz;
     geometry(p, &bx, &bz, &nbx, &nbz);
     const long long ntiles = (long long)nbx * nbz * p->ny;
-    const long long qs = plane_stride((long long)row_pitch(p) * p->ny * p->nz, elt);
+    const long long qs = plane_stride((long long)z_pitch(p, row_pitch(p)) * p->nz, elt);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -288,7 +314,8 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->elt = storage_bytes(p->storage);
     c->celt = p->storage == LBM_F64 ? 8 : 4;
     c->px = row_pitch(p);
-    c->qs = plane_stride((long long)c->px * p->ny * p->nz, c->elt);
+    c->zp = z_pitch(p, c->px);
+    c->qs = plane_stride((long long)c->zp * p->nz, c->elt);
     geometry(p, &c->bx, &c->bz, &c->nbx, &c->nbz);
     c->tpp = c->nbx * c->nbz;
     c->ntiles = c->tpp * p->ny;
@@ -467,7 +494,7 @@ lbm_status lbm_init(lbm_ctx *c, const double *rho, const double *u, int32_t on_d
         drho = tmp;
         du = tmp + n;
     }
-    HIPCHK(c, launch_init(c->p.storage, c->f, c->qs, c->p.nx, c->px, c->mom, drho, du, (int)n, c->stream),
+    HIPCHK(c, launch_init(c->p.storage, c->f, c->qs, c->p.nx, c->px, c->p.ny, c->zp, c->mom, drho, du, (int)n, c->stream),
            "lbm_init: kernel");
     if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_init: free staging");
     lbm_status s = reset_accumulators(c);
@@ -494,6 +521,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.ny = c->p.ny;
     a.nz = c->p.nz;
     a.px = c->px;
+    a.zp = c->zp;
     a.nbx = c->nbx;
     a.nbz = c->nbz;
     div_magic((uint32_t)a.nbx, &a.m_nbx, &a.s_nbx);
@@ -690,7 +718,7 @@ lbm_status lbm_set_f(lbm_ctx *c, const double *fin, int32_t on_device) {
     }
     // stored where the next step reads it: the AA parity of the context
     // continues (before the first step after lbm_init it is 0)
-    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, c->p.nx, c->px, c->p.ny, c->p.nz, c->parity,
+    HIPCHK(c, launch_set_f(c->p.storage, c->f, c->qs, src, c->p.nx, c->px, c->zp, c->p.ny, c->p.nz, c->parity,
                            c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_set_f: kernel");
     if (tmp) HIPCHK(c, hipFreeAsync(tmp, c->stream), "lbm_set_f: free staging");
     HIPCHK(c, hipStreamSynchronize(c->stream), "lbm_set_f: sync");
@@ -713,7 +741,7 @@ lbm_status lbm_get_f(lbm_ctx *c, double *fout, int32_t on_device) {
                "lbm_get_f: staging");
         dst = tmp;
     }
-    HIPCHK(c, launch_get_f(c->p.storage, c->f, c->qs, dst, c->p.nx, c->px, c->p.ny, c->p.nz, c->parity,
+    HIPCHK(c, launch_get_f(c->p.storage, c->f, c->qs, dst, c->p.nx, c->px, c->zp, c->p.ny, c->p.nz, c->parity,
                            c->p.bc_ylo, c->p.bc_yhi, c->stream), "lbm_get_f: kernel");
     if (tmp) {
         HIPCHK(c, hipMemcpyAsync(fout, tmp, (size_t)NQ * n * 8, hipMemcpyDeviceToHost, c->stream),

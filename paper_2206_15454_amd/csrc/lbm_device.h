@@ -301,7 +301,8 @@ struct StepArgs {
     void *f;          // population buffer, q-plane stride qs elements
     long long qs;
     int nx, ny, nz;
-    int px;           // population row pitch (cells, >= nx): cell (i,j,k) at (k ny + j) px + i
+    int px;           // population row pitch (cells, >= nx)
+    int zp;           // population z-layer pitch (cells, >= px ny): cell (i,j,k) at k zp + j px + i
     int nbx, nbz;     // tiles per row (x) and per column (z); tile = BX x 1 x BZ cells
     // division by nbx, nbz and ny as multiply and shift (div_magic)
     uint32_t m_nbx, m_nbz, m_ny;
@@ -365,14 +366,15 @@ __device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t m, int s) {
 
 // Launchers (defined in lbm_kernels.hip).
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s);
-// population arrays: rows of pitch px >= nx cells (cell (i,j,k) at (k ny + j) px + i)
-hipError_t launch_init(int storage, void *f, long long qs, int nx, int px, void *mom,
-                       const double *rho, const double *u, int n, hipStream_t s);
+// population arrays: rows of pitch px >= nx cells, z-layers of pitch zp >= px ny
+// cells (cell (i,j,k) at k zp + j px + i)
+hipError_t launch_init(int storage, void *f, long long qs, int nx, int px, int ny, int zp,
+                       void *mom, const double *rho, const double *u, int n, hipStream_t s);
 // populations [19][N] into the slots the next step of the given AA parity reads
 hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int px,
-                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);
+                        int zp, int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);
 hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int px,
-                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);  // EQ stores like BB
+                        int zp, int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s);  // EQ stores like BB
 hipError_t launch_moments_out(int storage, const void *mom, double *rho, double *u,
                               double *nut, int n, hipStream_t s);
 // FP64 diagnostics into out[9] (mass, mom[3], impulse[3], max|u|, nonfinite):

@@ -101,21 +101,28 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // j) or, with FLAG_MEMORDER and in the learned-closure kernel, memory
     // order (then the row j, then the z tile), in which the tiles that run at
     // the same time touch neighbouring rows of each plane
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int rest = (int)div_by((uint32_t)tile, a.m_nbx, a.s_nbx);
     const int bx = tile - rest * a.nbx;
     int j, bz;  // the whole block lies in row j
     if (LEARNED || (a.flags & FLAG_MEMORDER) != 0) {
         bz = (int)div_by((uint32_t)rest, a.m_ny, a.s_ny);
-        j = rest - bz * a.ny;
+        j = rest - bz * ny;
     } else {
         j = (int)div_by((uint32_t)rest, a.m_nbz, a.s_nbz);
         bz = rest - j * a.nbz;
     }
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int i = bx * (int)blockDim.x + (int)threadIdx.x;
     const int k = bz * (int)blockDim.y + (int)threadIdx.y;
     const bool active = (i < nx) && (k < nz);
     const int ic = i < nx ? i : nx - 1;  // clamped: inactive lanes load valid memory
+    // pad lanes (on a padded row's cells nx <= i < px) load and store their
+    // own pad cells, x offsets 0, so that every cache line of the row is
+    // written whole (rows whose last line was written in part ran 6 % slower
+    // at 350 cells); they never touch a cell of the grid, and no cell reads
+    // their values
+    const int px = a.px;
+    const bool pad = (i >= nx) && (i < px) && (k < nz);
     const int kc = k < nz ? k : nz - 1;
 
     // neighbour coordinates with periodic wrap (y wraps only if periodic;
@@ -126,11 +133,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     // self: the cell's dense index (moments, forest index, rounding hash);
     // pself: its population index, rows laid out with the pitch px >= nx
     // (rows padded to whole cache lines)
-    const int px = a.px;
-    const int plane = px * ny;
+    const int plane = a.zp;  // z-layer pitch (>= px ny)
     const int self = (kc * ny + j) * nx + ic;
-    const int pself = (kc * ny + j) * px + ic;
-    const int xo[3] = {ic == 0 ? nx - 1 : -1, 0, ic == nx - 1 ? 1 - nx : 1};
+    const int pself = kc * plane + j * px + (pad ? i : ic);
+    const int xo[3] = {pad ? 0 : ic == 0 ? nx - 1 : -1, 0, pad ? 0 : ic == nx - 1 ? 1 - nx : 1};
     const int yo[3] = {(j == 0 ? ny - 1 : -1) * px, 0, (j == ny - 1 ? 1 - ny : 1) * px};
     const int zo[3] = {kc == 0 ? (nz - 1) * plane : -plane, 0,
                        kc == nz - 1 ? (1 - nz) * plane : plane};
@@ -322,7 +328,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         short z[16];
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-            in_range = in_range && (x[c] >= mc->lo[c]) && (x[c] <= mc->hi[c]);
+            in_range = in_range && active && (x[c] >= mc->lo[c]) && (x[c] <= mc->hi[c]);
             z[c] = bf16_bits(x[c] * mc->zs[c] + mc->zo[c]);
         }
         z[9] = z[10] = bf16_bits(1.0f);
@@ -456,7 +462,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
             });
         }
     };
-    if (active) {
+    if (active || pad) {
         if constexpr (!LEARNED)
             store(std::bool_constant<kStream>{});
         else if (streaming)
@@ -533,9 +539,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         }
     }
     if (a.flags & FLAG_STATS) {
-        const C m = active ? C(1) : C(0);
-        const C sv[10] = {m * ux,      m * uy,      m * uz,      m * ux * ux, m * uy * uy,
-                          m * uz * uz, m * ux * uy, m * ux * uz, m * uy * uz, m * nut};
+        // selects, not products with 0 or 1: a pad lane's values may be
+        // non-finite
+        auto m = [&](C v) { return active ? v : C(0); };
+        const C sv[10] = {m(ux),      m(uy),      m(uz),      m(ux * ux), m(uy * uy),
+                          m(uz * uz), m(ux * uy), m(ux * uz), m(uy * uz), m(nut)};
         const long long slot = ((long long)j * (a.nbx * a.nbz) + bz * a.nbx + bx) * 10;
         block_accumulate<10>(sv, a.stats + slot, sh);
     }
@@ -597,15 +605,16 @@ void lbm_step_mlp_kernel(const StepArgs a) {
 // layout a neighbour step reads (slot opp(q) of the own cell).
 template <int ST>
 __global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, int nx, int px,
-                                                   void *mom, const double *rho, const double *u,
-                                                   int n) {
+                                                   int ny, int zp, void *mom, const double *rho,
+                                                   const double *u, int n) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     T *f = static_cast<T *>(fp);
-    const long long xp = (long long)(x / nx) * px + x % nx;  // population index (row pitch px)
+    const int row = x / nx;  // population index: rows of pitch px, z-layers of pitch zp
+    const long long xp = (long long)(row / ny) * zp + (long long)(row % ny) * px + x % nx;
     const double r = rho[x], ux = u[x], uy = u[n + x], uz = u[2 * (long long)n + x];
     const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
     static_for<NQ>([&](auto qc) {
@@ -628,10 +637,11 @@ __global__ __launch_bounds__(256) void init_kernel(void *fp, long long qs, int n
 // next) slot opp(q) of x; after a neighbour step (parity 1 next) where the
 // neighbour step wrote it (slot q of x + c_q, or the wall's slot).  A
 // bijection of the 19 N slots (every cell reads and writes the same 19).
-__device__ __forceinline__ long long slot_of(int q, int i, int j, int k, int nx, int px, int ny,
-                                             int nz, int parity, int bc_lo, int bc_hi,
+__device__ __forceinline__ long long slot_of(int q, int i, int j, int k, int nx, int px, int zp,
+                                             int ny, int nz, int parity, int bc_lo, int bc_hi,
                                              long long qs) {
-    const long long own = ((long long)k * ny + j) * px + i;  // rows of pitch px
+    // rows of pitch px, z-layers of pitch zp
+    const long long own = (long long)k * zp + (long long)j * px + i;
     if (parity == 0) return opp(q) * qs + own;
     const int cx = CX[q], cy = CY[q], cz = CZ[q];
     const int it = (i + cx + nx) % nx, kt = (k + cz + nz) % nz;
@@ -639,15 +649,15 @@ __device__ __forceinline__ long long slot_of(int q, int i, int j, int k, int nx,
     if (cy != 0 && (jt < 0 || jt >= ny) && (jt < 0 ? bc_lo : bc_hi) != BC_PERIODIC) {
         if ((jt < 0 ? bc_lo : bc_hi) != BC_FREESLIP)  // bounce-back or forced equilibrium
             return opp(q) * qs + own;
-        return mir(q) * qs + ((long long)kt * ny + j) * px + it;
+        return mir(q) * qs + (long long)kt * zp + (long long)j * px + it;
     }
-    return q * qs + ((long long)kt * ny + (jt + ny) % ny) * px + it;
+    return q * qs + (long long)kt * zp + (long long)((jt + ny) % ny) * px + it;
 }
 
 template <int ST>
 __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, const double *fin,
-                                                    int nx, int px, int ny, int nz, int parity,
-                                                    int bc_lo, int bc_hi) {
+                                                    int nx, int px, int zp, int ny, int nz,
+                                                    int parity, int bc_lo, int bc_hi) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     using C = typename CD::C;
@@ -660,7 +670,7 @@ __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, cons
     const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const long long at = slot_of(q, i, j, k, nx, px, ny, nz, parity, bc_lo, bc_hi, qs);
+        const long long at = slot_of(q, i, j, k, nx, px, zp, ny, nz, parity, bc_lo, bc_hi, qs);
         CD::st(f + at, (C)(fin[(long long)q * n + x] - weight(q)));
     });
 }
@@ -670,8 +680,8 @@ __global__ __launch_bounds__(256) void set_f_kernel(void *fp, long long qs, cons
 // (parity 1 next) where the neighbour step wrote them.
 template <int ST>
 __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs, double *fout,
-                                                    int nx, int px, int ny, int nz, int parity,
-                                                    int bc_lo, int bc_hi) {
+                                                    int nx, int px, int zp, int ny, int nz,
+                                                    int parity, int bc_lo, int bc_hi) {
     using CD = Codec<ST>;
     using T = typename CD::T;
     const long long n = (long long)nx * ny * nz;
@@ -683,7 +693,7 @@ __global__ __launch_bounds__(256) void get_f_kernel(const void *fp, long long qs
     const int k = (int)(x / ((long long)nx * ny));
     static_for<NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const long long at = slot_of(q, i, j, k, nx, px, ny, nz, parity, bc_lo, bc_hi, qs);
+        const long long at = slot_of(q, i, j, k, nx, px, zp, ny, nz, parity, bc_lo, bc_hi, qs);
         fout[q * n + x] = (double)CD::ld(f + at) + weight(q);
     });
 }
@@ -957,26 +967,28 @@ hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, int g
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, void *f, long long qs, int nx, int px, void *mom,
-                       const double *rho, const double *u, int n, hipStream_t s) {
+hipError_t launch_init(int storage, void *f, long long qs, int nx, int px, int ny, int zp,
+                       void *mom, const double *rho, const double *u, int n, hipStream_t s) {
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, nx, px, mom, rho, u, n));
+                                              s, f, qs, nx, px, ny, zp, mom, rho, u, n));
     return hipGetLastError();
 }
 
 hipError_t launch_set_f(int storage, void *f, long long qs, const double *fin, int nx, int px,
-                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+                        int zp, int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(set_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, fin, nx, px, ny, nz, parity, bc_lo, bc_hi));
+                                              s, f, qs, fin, nx, px, zp, ny, nz, parity, bc_lo,
+                                              bc_hi));
     return hipGetLastError();
 }
 
 hipError_t launch_get_f(int storage, const void *f, long long qs, double *fout, int nx, int px,
-                        int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
+                        int zp, int ny, int nz, int parity, int bc_lo, int bc_hi, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     LBMX_DISPATCH_AUX(storage, hipLaunchKernelGGL(get_f_kernel<S>, dim3(blocks_for(n)), dim3(256), 0,
-                                              s, f, qs, fout, nx, px, ny, nz, parity, bc_lo, bc_hi));
+                                              s, f, qs, fout, nx, px, zp, ny, nz, parity, bc_lo,
+                                              bc_hi));
     return hipGetLastError();
 }
 

@@ -218,16 +218,21 @@ def test_streaming_cache_policy_changes_nothing(monkeypatch, storage, nx):
 @pytest.mark.parametrize("storage,nx", [("f32", 70), ("bf16sr", 67), ("f16s", 100), ("f64", 35)])
 def test_row_pitch_changes_nothing(monkeypatch, storage, nx):
     """Population rows padded to whole 128-byte lines (the default when a row
-    is not; LBMX_PITCH=0 keeps them dense) give bit-identical populations,
-    moments and diagnostics, both AA parities, walls included; with the
-    learned closure too."""
+    is not; LBMX_PITCH=0 keeps them dense), and z-layers padded beyond px ny
+    cells (LBMX_ZALIGN, LBMX_ZPAD), give bit-identical populations, moments
+    and diagnostics, both AA parities, walls included; with the learned
+    closure too."""
     from paper_2206_15454_amd import closure
 
     w = inputs.scaled(inputs.C1, nx, 9, 6, canopy_rows=4)
     blob = closure.timing_blob(10.0)
     res = []
-    for pitch in ("0", "1"):
+    # dense, padded rows, padded rows in z-layers rounded to 4 KiB, dense
+    # rows in z-layers widened by 384 B
+    for pitch, zalign, zpad in (("0", "", ""), ("1", "", ""), ("1", "4096", ""), ("0", "", "384")):
         monkeypatch.setenv("LBMX_PITCH", pitch)
+        monkeypatch.setenv("LBMX_ZALIGN", zalign)
+        monkeypatch.setenv("LBMX_ZPAD", zpad)
         out = []
         for learned in (False, True):
             _, g = make_pair(w, storage=storage, seed=10)
@@ -238,9 +243,10 @@ def test_row_pitch_changes_nothing(monkeypatch, storage, nx):
             out.append((g.get_f(), r, u, nt, d["mass"], d["mlp_fallback"]))
             g.close()
         res.append(out)
-    for a, b in zip(res[0], res[1]):
-        for x, y in zip(a, b):
-            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
