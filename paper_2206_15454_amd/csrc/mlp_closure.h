@@ -108,6 +108,28 @@ __device__ __forceinline__ half2v mlp_gelu_h2(half2v x) {
     return x * s;
 }
 
+// Two independent pairs at once, the two evaluations step by step side by
+// side: each instruction of one separates the dependent instructions of the
+// other (a lone chain waits between its dependent packed instructions).
+__device__ __forceinline__ void mlp_gelu_h2x2(half2v &xa, half2v &xb) {
+    auto k = [](float v) { return half2v{(_Float16)v, (_Float16)v}; };
+    const half2v ya = xa * xa, yb = xb * xb;
+    half2v pa = __builtin_elementwise_fma(ya, k(1.710653305053711e-05f), k(-5.578994750976562e-04f));
+    half2v pb = __builtin_elementwise_fma(yb, k(1.710653305053711e-05f), k(-5.578994750976562e-04f));
+    pa = __builtin_elementwise_fma(pa, ya, k(7.762908935546875e-03f));
+    pb = __builtin_elementwise_fma(pb, yb, k(7.762908935546875e-03f));
+    pa = __builtin_elementwise_fma(pa, ya, k(-6.2744140625e-02f));
+    pb = __builtin_elementwise_fma(pb, yb, k(-6.2744140625e-02f));
+    pa = __builtin_elementwise_fma(pa, ya, k(3.96728515625e-01f));
+    pb = __builtin_elementwise_fma(pb, yb, k(3.96728515625e-01f));
+    half2v sa = __builtin_elementwise_fma(xa, pa, k(0.5f));
+    half2v sb = __builtin_elementwise_fma(xb, pb, k(0.5f));
+    sa = __builtin_elementwise_min(__builtin_elementwise_max(sa, k(0.0f)), k(1.0f));
+    sb = __builtin_elementwise_min(__builtin_elementwise_max(sb, k(0.0f)), k(1.0f));
+    xa = xa * sa;
+    xb = xb * sb;
+}
+
 __device__ __forceinline__ float mlp_softplus(float x) {
     return x > 20.0f ? x : __logf(1.0f + __expf(x));
 }
@@ -172,8 +194,9 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short 
         for (int u = 0; u < 4; ++u) {
             const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
             floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[u], zb, zero, 0, 0, 0);
-            const half2v g0 = mlp_gelu_h2(half2v{(_Float16)d[0], (_Float16)d[1]});
-            const half2v g1 = mlp_gelu_h2(half2v{(_Float16)d[2], (_Float16)d[3]});
+            half2v g0 = half2v{(_Float16)d[0], (_Float16)d[1]};
+            half2v g1 = half2v{(_Float16)d[2], (_Float16)d[3]};
+            mlp_gelu_h2x2(g0, g1);
             const int o = (u & 1) * 4;
             x2[ct][u >> 1][o] = g0[0];
             x2[ct][u >> 1][o + 1] = g0[1];
@@ -202,8 +225,9 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpFrag &f, const short 
                 const int u = 2 * ks + p;
                 floatx4 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[p][0], x2[ct][0], f.b2[u], 0, 0, 0);
                 e = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[p][1], x2[ct][1], e, 0, 0, 0);
-                const half2v g0 = mlp_gelu_h2(half2v{(_Float16)e[0], (_Float16)e[1]});
-                const half2v g1 = mlp_gelu_h2(half2v{(_Float16)e[2], (_Float16)e[3]});
+                half2v g0 = half2v{(_Float16)e[0], (_Float16)e[1]};
+                half2v g1 = half2v{(_Float16)e[2], (_Float16)e[3]};
+                mlp_gelu_h2x2(g0, g1);
                 x3[4 * p] = g0[0];
                 x3[4 * p + 1] = g0[1];
                 x3[4 * p + 2] = g1[0];
