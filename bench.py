@@ -202,6 +202,9 @@ def main():
     ap.add_argument("--mlp-canopy-every", default="1,8",
                     help="intervals timed with the closure restricted to the canopy layer "
                          "(y/h <= 4, Smagorinsky above)")
+    ap.add_argument("--mlp-also", default="f16s",
+                    help="other storage types timed with the learned closure every step, "
+                         "everywhere and in the canopy layer ('' for none)")
     ap.add_argument("--c5", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 1024x256x512 pair of the learned-closure comparison: "
                          "FP32 + Smagorinsky against low-precision storage + learned closure")
@@ -288,11 +291,17 @@ def main():
         # the network trained on the canopy case at twice the resolution, used
         # everywhere and restricted to the canopy layer (a wavefront whose cells
         # all fall back skips the network, so the restriction is faster)
-        runs = [(closure.trained_blob(), int(e), "") for e in args.mlp_every.split(",") if e]
-        runs += [(closure.canopy_layer_blob(), int(e), "(y<4h)")
+        st = args.mlp_storage
+        runs = [(st, closure.trained_blob(), int(e), "") for e in args.mlp_every.split(",") if e]
+        runs += [(st, closure.canopy_layer_blob(), int(e), "(y<4h)")
                  for e in args.mlp_canopy_every.split(",") if e]
-        for blob, every, tag in runs:
-            sim = make_sim(w, args.mlp_storage, lbm, inputs)
+        for other in (x for x in args.mlp_also.split(",") if x and x != st):
+            if other not in BYTES_PER_ELT:
+                raise SystemExit(f"--mlp-also: unknown storage {other!r}")
+            runs += [(other, closure.trained_blob(), 1, ""),
+                     (other, closure.canopy_layer_blob(), 1, "(y<4h)")]
+        for st, blob, every, tag in runs:
+            sim = make_sim(w, st, lbm, inputs)
             sim.init(rho_d, u_d)
             sim.set_closure(blob)
             sim.set_closure_interval(every)
@@ -301,10 +310,10 @@ def main():
             sim.close()
             # steps that reuse nu_t also read it (4 B/cell FP32, 8 B FP64);
             # evaluating steps write it when it is reused
-            nb = 8 if args.mlp_storage == "f64" else 4
-            b = (2 * 19 * BYTES_PER_ELT[args.mlp_storage] + extra) * w.n
+            nb = 8 if st == "f64" else 4
+            b = (2 * 19 * BYTES_PER_ELT[st] + extra) * w.n
             b += (nb * w.n if every > 1 else 0)
-            name = args.mlp_storage + "+mlp" + tag + ("" if every == 1 else f"/{every}")
+            name = st + "+mlp" + tag + ("" if every == 1 else f"/{every}")
             v = w.n * k / (t_ms * 1e-3) / 1e6
             variants[name] = {"MLUPS": round(v, 1), "vs_" + args.storage: round(v / mlups, 3),
                               "hbm_frac": round(b / (s_ms * 1e-3 / k) / 1e9 / HBM_PEAK_GBS, 4),

@@ -407,7 +407,9 @@ def layer_study(out, cut=4.0, coarse_steps=20000, avg_from=10000):
             "bf16sr_mlp_every1": ("bf16sr", full, 0.0, 1),
             f"bf16sr_mlp_below{cut:g}h_every1": ("bf16sr", low, 0.0, 1),
             f"bf16sr_mlp_below{cut:g}h_every8": ("bf16sr", low, 0.0, 8),
-            f"f32_mlp_below{cut:g}h_every1": ("f32", low, 0.0, 1)}
+            f"f32_mlp_below{cut:g}h_every1": ("f32", low, 0.0, 1),
+            "f16s_mlp_every1": ("f16s", full, 0.0, 1),
+            f"f16s_mlp_below{cut:g}h_every1": ("f16s", low, 0.0, 1)}
     res = {"workload": wc.name, "cut_y_over_h": cut, "steps": coarse_steps,
            "avg_from": avg_from, "runs": {}, "errors": {}, "profiles": {}}
     profs = {}
