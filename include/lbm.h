@@ -141,8 +141,10 @@ size_t lbm_required_bytes(const lbm_params *p);
  *   LBMX_PITCH=0|1          population rows padded to whole 128-byte lines
  *                           (default: for population arrays above 256 MiB,
  *                           rows of nx cells that are not whole lines get a
- *                           pitch of the next whole number of lines; the pad
- *                           cells are never touched) */
+ *                           pitch of the next whole number of lines; the
+ *                           step writes values of no meaning to the pad
+ *                           cells, so that every line is written whole, and
+ *                           no cell of the grid reads them) */
 lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_ctx **out);
 
 /* Release the context (and its device memory if the library allocated it). */

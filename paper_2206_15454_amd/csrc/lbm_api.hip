@@ -186,8 +186,9 @@ bool large_array(const lbm_params *p) {
 // Population row pitch: for the arrays that stream, rows padded to whole
 // 128-byte lines, so that every row starts on a line and the row-aligned
 // accesses can stream (rows of 350 FP32 cells, 1 400 B, otherwise share
-// their end lines with the next row).  The padding cells are never read or
-// written.  No padding when a row is already whole lines, for arrays that do
+// their end lines with the next row).  The step stores values of no meaning
+// to the padding cells (whole lines are written; no cell of the grid reads
+// them).  No padding when a row is already whole lines, for arrays that do
 // not stream, or when the padded array would not be indexable in 32 bits.
 // LBMX_PITCH=0|1 forces dense rows or padded rows (the populations are
 // bit-identical either way).
