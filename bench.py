@@ -14,6 +14,7 @@ Prints one JSON line.  value = cells * steps / time / 1e6 (MLUPS).
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -37,10 +38,16 @@ KERNEL_SOURCES = ("paper_2206_15454_amd/csrc/lbm_kernels.hip",
 
 
 def kernel_hash():
+    """Hash of the step kernels' source with its comments removed (an edit
+    of a comment leaves the compiled kernels, and so their counters, as they
+    were; the sources hold no comment markers inside string literals)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 
