@@ -20,14 +20,21 @@ def _tree(tmp_path):
 
 
 def test_kernel_hash_tracks_every_source(monkeypatch, tmp_path):
+    """A code edit in any hashed source changes the hash; comments, blank
+    lines and trailing blanks do not (they leave the compiled kernels as
+    they were)."""
     _tree(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.kernel_hash()
     assert len(h0) == 16 and h0 == bench.kernel_hash()
     seen = {h0}
-    for p in bench.KERNEL_SOURCES:
+    for i, p in enumerate(bench.KERNEL_SOURCES):
+        seen_last = bench.kernel_hash()
         with open(tmp_path / p, "a") as f:
-            f.write("\n// edit\n")
+            f.write("\n// a comment\n/* another\n   one */   \n\n")
+        assert bench.kernel_hash() == seen_last, p
+        with open(tmp_path / p, "a") as f:
+            f.write(f"static int edit_{i};\n")
         h = bench.kernel_hash()
         assert h not in seen, p
         seen.add(h)
