@@ -126,15 +126,18 @@ size_t lbm_required_bytes(const lbm_params *p);
  *                           multiple of 128; default: neither)
  *   LBMX_QPAD=bytes         pad between population planes (default 2048 for
  *                           the 16-bit types, 1024 otherwise)
- *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1)
+ *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1, but 0
+ *                           for the step of FP32 and FP64 arrays above
+ *                           256 MiB; the learned-closure kernel keeps 1)
  *   LBMX_WIDE=0|1           64-bit population addresses (default: only when
  *                           buffer resources cannot address the array)
  *   LBMX_STREAMING=0|1      non-temporal population accesses (default: when
  *                           the population array exceeds 256 MiB and a row
  *                           is a whole number of 128-byte lines)
  *   LBMX_TILE_ORDER=0|1     row-major or memory-order tile numbering (default:
- *                           memory order unless rows stream and a plane is at
- *                           most 96 MiB)
+ *                           memory order for FP32 and FP64 arrays above
+ *                           256 MiB, otherwise unless rows stream and a plane
+ *                           is at most 96 MiB)
  *   LBMX_FX=0|1             kernels that leave out the y and z force terms
  *                           when g_y = g_z = 0 and the drag is x-only
  *                           (default 1)
