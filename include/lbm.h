@@ -126,9 +126,12 @@ size_t lbm_required_bytes(const lbm_params *p);
  *                           multiple of 128; default: neither)
  *   LBMX_QPAD=bytes         pad between population planes (default 2048 for
  *                           the 16-bit types, 1024 otherwise)
- *   LBMX_XCD_REMAP=0|1      contiguous tile ranges per XCD (default 1, but 0
- *                           for the step of FP32 and FP64 arrays above
- *                           256 MiB; the learned-closure kernel keeps 1)
+ *   LBMX_XCD_REMAP=0|1      one contiguous tile range per XCD (default 1;
+ *                           0: blocks go to the XCDs round robin)
+ *   LBMX_XCD_RUN=tiles      the XCDs take turns in runs of this many tiles
+ *                           (default: 2 for the step of FP32 and 4 for FP64
+ *                           arrays above 256 MiB; the learned-closure
+ *                           kernel keeps one range per XCD)
  *   LBMX_WIDE=0|1           64-bit population addresses (default: only when
  *                           buffer resources cannot address the array)
  *   LBMX_STREAMING=0|1      non-temporal population accesses (default: when

@@ -35,6 +35,7 @@ struct lbm_ctx {
     int bx = 256, bz = 1, nbx = 1, nbz = 1, ntiles = 1, tpp = 1;
     bool xcd_remap = true;    // plain step: contiguous tile ranges per XCD (FLAG_XCD_REMAP)
     bool mlp_remap = true;    // the same for the learned-closure kernel's walk
+    int xcd_run = 0;          // plain step: runs of tiles per XCD (0: one range)
     bool force_wide = false;  // 64-bit population addresses even for small planes
     bool fx = true;           // the x-only-force kernels when the force is along x (VAR_FX)
     bool streaming = false;   // non-temporal accesses on aligned rows (FLAG_STREAMING)
@@ -336,24 +337,39 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     // cache lines (350x140x280: +7 %).  The switch is at 96 MiB.
     // LBMX_TILE_ORDER=0/1 overrides.
     c->memorder = !c->streaming || (unsigned long long)c->qs * c->elt > (96ULL << 20);
-    // FP32 and FP64 arrays beyond the Infinity Cache: memory order with the
-    // blocks handed to the XCDs round robin (no remap), so that the XCDs work
-    // side by side in one stretch of each plane instead of in eight distant
-    // ones: +4.8 % (FP32) and +6.6 % (FP64) at 512x128x256, +4.3 % at
-    // 1024x256x512, +3.6 / +4.6 % at 350x140x280 and +7.5 / +9 % at
-    // 250x100x200 against the better of the two orders with the remap.  The
-    // 16-bit types measured best with the choice above and the remap (up to
-    // 10 % slower without it at 512x128x256), and so did FP32 on arrays that
-    // fit the cache (200x80x160).  The learned-closure kernel keeps its
-    // remapped walk.  LBMX_TILE_ORDER=0/1 and LBMX_XCD_REMAP=0/1 override.
+    // FP32 and FP64 arrays beyond the Infinity Cache: memory order, the
+    // XCDs taking turns in short runs of tiles (2 for FP32, 4 for FP64), so
+    // that they work side by side in one stretch of each plane instead of in
+    // eight distant ones.  Against the better of the two orders with one
+    // contiguous range per XCD: +4.8 % (FP32) and +6.6 % (FP64) at
+    // 512x128x256, +4.3 % at 1024x256x512, +3.6 / +4.6 % at 350x140x280,
+    // +7.5 / +9 % at 250x100x200 with single tiles taking turns.  Runs of 1
+    // to 16 tiles: these lengths came within 1 % of the best at 512x128x256,
+    // 1024x256x512, 350x140x280 and 250x100x200 (single tiles: FP32 -1.6 %
+    // at 512x128x256 and -2 % at 350x140x280, FP64 -6 % at 1024x256x512;
+    // runs of 8: FP32 -3.7 % at 1024x256x512).  The 16-bit types measured best with the choice
+    // above and one range per XCD (within 1 % of memory order with runs of
+    // 16; up to 10 % slower with single tiles), and so did FP32 on arrays
+    // that fit the cache (200x80x160).  The learned-closure kernel keeps its
+    // remapped walk.  LBMX_TILE_ORDER=0/1, LBMX_XCD_REMAP=0/1 and
+    // LBMX_XCD_RUN=tiles override.
     c->xcd_remap = true;
     if (large_array(p) && c->elt >= 4) {
         c->memorder = true;
-        c->xcd_remap = false;
+        c->xcd_run = c->elt == 8 ? 4 : 2;
     }
     if (const char *e = std::getenv("LBMX_TILE_ORDER")) c->memorder = std::atoi(e) != 0;
-    if (const char *e = std::getenv("LBMX_XCD_REMAP"))
+    if (const char *e = std::getenv("LBMX_XCD_REMAP")) {
         c->xcd_remap = c->mlp_remap = std::atoi(e) != 0;
+        c->xcd_run = 0;
+    }
+    if (const char *e = std::getenv("LBMX_XCD_RUN")) {
+        const int v = std::atoi(e);
+        if (v > 0) {
+            c->xcd_run = v;
+            c->xcd_remap = true;
+        }
+    }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LBM_EDEVICE;
@@ -546,6 +562,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     div_magic((uint32_t)a.nbz, &a.m_nbz, &a.s_nbz);
     div_magic((uint32_t)c->p.ny, &a.m_ny, &a.s_ny);
     a.ntiles = c->ntiles;
+    a.xcd_run = c->xcd_run;
     a.bc_lo = c->p.bc_ylo;
     a.bc_hi = c->p.bc_yhi;
     a.tau0 = c->p.tau0;

@@ -308,6 +308,7 @@ struct StepArgs {
     uint32_t m_nbx, m_nbz, m_ny;
     int s_nbx, s_nbz, s_ny;
     int ntiles;       // nbx * nbz * ny = grid size
+    int xcd_run;      // FLAG_XCD_REMAP: 0 = one contiguous range per XCD, else runs of this many tiles
     int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
     int bc_lo, bc_hi;
     int flags;
@@ -349,6 +350,17 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int q = n >> 3, r = n & 7;
     const int x = b & 7, local = b >> 3;
     return x * q + (x < r ? x : r) + local;
+}
+
+// The same with runs of c consecutive tiles: XCD x takes the runs x, x + 8,
+// x + 16, ... of the first n - n % (8 c) tiles, in order; the tiles after
+// them keep their block (a bijection of [0, n)).
+__device__ __forceinline__ int xcd_remap_runs(int b, int n, int c) {
+    const int full = n - n % (8 * c);
+    if (b >= full) return b;
+    const int x = b & 7, local = b >> 3;
+    const int run = local / c;
+    return (run * 8 + x) * c + (local - run * c);
 }
 
 // Division of 0 <= n < 2^31 by a constant d >= 1 as n * m >> s (Granlund and

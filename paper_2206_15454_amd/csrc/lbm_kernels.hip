@@ -553,7 +553,8 @@ template <int ST, int VAR>
 __global__ __launch_bounds__(256) void lbm_step_kernel(const StepArgs a) {
     __shared__ double sh[4 * 10];
     int tile = blockIdx.x;
-    if (a.flags & FLAG_XCD_REMAP) tile = xcd_remap(tile, a.ntiles);
+    if (a.flags & FLAG_XCD_REMAP)
+        tile = a.xcd_run > 0 ? xcd_remap_runs(tile, a.ntiles, a.xcd_run) : xcd_remap(tile, a.ntiles);
     double unused[3] = {0.0, 0.0, 0.0};
     unsigned nofb = 0;
     step_tile<ST, false, VAR>(a, tile, MlpFrag{}, nullptr, nullptr, sh, unused, nullptr, nofb);

@@ -291,6 +291,30 @@ def test_tile_order_changes_nothing(monkeypatch, storage):
     np.testing.assert_array_equal(res[1], res[0])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
+def test_xcd_runs_change_nothing(monkeypatch, storage):
+    """The XCDs taking turns in runs of 1, 2, 4 or 6 tiles (LBMX_XCD_RUN;
+    the tiles past the last whole round keep their block), one contiguous
+    range per XCD and no remap give bit-identical populations and moments,
+    in both tile orders.  200x9x12 has 108 tiles: a run of 4 or 6 covers
+    96 of them in whole rounds."""
+    w = inputs.scaled(inputs.C1, 200, 9, 12, canopy_rows=3)
+    res = []
+    for order in ("0", "1"):
+        for remap, run in (("1", ""), ("0", ""), ("1", "1"), ("1", "2"), ("1", "4"), ("1", "6")):
+            monkeypatch.setenv("LBMX_TILE_ORDER", order)
+            monkeypatch.setenv("LBMX_XCD_REMAP", remap)
+            monkeypatch.setenv("LBMX_XCD_RUN", run)
+            _, g = make_pair(w, storage=storage, seed=12)
+            g.step(5)
+            r, u, nt, d = g.moments()
+            res.append((g.get_f(), r, u, nt))
+            g.close()
+    for other in res[1:]:
+        for x, y in zip(res[0], other):
+            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+
+
 def test_errors_and_state_machine():
     from paper_2206_15454_amd import lbm
 
