@@ -1,0 +1,81 @@
+"""The step at full size, in the launch configuration the benchmark times,
+against the oracle on a slab of sampled cells.
+
+The 512x128x256 canopy case is above 256 MiB in FP32 and FP64, so its rows
+stream, its tiles run in memory order and the XCDs take turns in runs of
+2 (FP32) or 4 (FP64) tiles; in BF16SR the tiles run in row-major order with
+one contiguous range per XCD.  These choices are made for arrays of this
+size only.  The GPU takes one step of the whole grid from a state it reached
+itself; the oracle takes the same step on a z-slab of 16 rows of that state,
+periodic in z: its 14 inner rows see the same 19 neighbours as in the whole
+grid, and are compared cell by cell, for both AA parities.
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2206_15454_amd import inputs
+from tests.gpu_common import oracle_lad, require_gpu, round_storage, ulp
+
+pytestmark = pytest.mark.gpu
+
+K0, SLAB = 101, 16  # the slab k0 .. k0 + 15 of the 256 z rows
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16sr"])
+def test_full_size_step_matches_oracle_on_a_slab(storage):
+    import torch
+
+    from paper_2206_15454_amd import lbm
+
+    w = inputs.C2
+    _, W = ref.lattice()
+    W4 = W[:, None, None, None]
+    lad = oracle_lad(w)
+    g = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                u_wall=w.u_wall)
+    g.set_canopy(w.cd, lad, False)
+    rho, u = inputs.init_fields_torch(w, torch.device("cuda"), seed=11)
+    g.init(rho, u)
+    del rho, u
+    g.step(20)
+    o = ref.RefLBM(w.nx, w.ny, SLAB, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    o.set_wall_velocity(w.u_wall)
+    o.set_canopy(w.cd, lad, False)
+    slab = g.get_f()[:, K0:K0 + SLAB].copy()
+    for parity in (0, 1):
+        o.set_f(slab)
+        o.step(1)
+        g.step(1)
+        full = g.get_f()
+        sg = full[:, K0 + 1:K0 + SLAB - 1] - W4
+        so = o.get_f()[:, 1:SLAB - 1] - W4
+        slab = full[:, K0:K0 + SLAB].copy()
+        del full
+        err = np.abs(sg - so)
+        if storage == "f64":
+            # 16 FP64 ulps of the largest population (the oracle rounds
+            # relative to |f|, the GPU relative to |f - w|)
+            bound = 16 * 2.0 ** -53 * np.max(np.abs(so + W4))
+        else:
+            # 1 ulp of the storage type at the value + 8 FP32 ulps of the
+            # population's own scale w_q rho (rho ~ 1).  The collision forms
+            # terms of that size (w_q rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u) / tau,
+            # with u ~ 0.1 and 1 / tau ~ 2 at tau0 = 0.5005) in FP32, so its
+            # rounding is a few ulps of w_q, not of the small shifted value
+            # f - w_q; the one-step test of near-rest random states, whose
+            # shifted values are small in every direction, uses the tighter
+            # scale of the shifted value
+            bound = ulp(so, storage) + 8 * 2.0 ** -24 * W4
+        worst = float(np.max(err / bound))
+        per_q = np.max(err / bound, axis=(1, 2, 3))
+        print(storage, "parity", parity, "max err/bound", worst, "cells", sg[0].size,
+              "per direction", np.round(per_q, 3).tolist())
+        assert worst <= 1.0
+        np.testing.assert_array_equal(round_storage(sg, storage), sg)
+    g.close()
