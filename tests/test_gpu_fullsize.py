@@ -79,3 +79,67 @@ def test_full_size_step_matches_oracle_on_a_slab(storage):
         assert worst <= 1.0
         np.testing.assert_array_equal(round_storage(sg, storage), sg)
     g.close()
+
+
+def test_full_size_learned_step_matches_oracle_on_a_slab():
+    """The persistent learned-closure kernel at full size (512x128x256,
+    BF16SR, the trained network with its input ranges opened so that every
+    cell evaluates it, as the benchmark's 1024x256x512 comparison does): one
+    step of each AA parity from the GPU's own state after 20 steps (the
+    Smagorinsky closure), against the oracle on the 16-row z-slab.  Bounds
+    as the learned-closure parity test: nu_t within 3e-2 of its largest
+    value (layer-1 BF16 operands, FP16 activations and layer 2, polynomial
+    GELU); the populations within 1 ulp of BF16 + 8 FP32 ulps of w_q + the
+    effect of that nu_t bound on the relaxation, |f - f_eq| 3 dnu / tau^2
+    with |f - f_eq| <= 2 max |f~|; no fallback on either side."""
+    import torch
+
+    from paper_2206_15454_amd import closure, lbm
+
+    w = inputs.C2
+    storage = "bf16sr"
+    _, W = ref.lattice()
+    W4 = W[:, None, None, None]
+    lad = oracle_lad(w)
+    blob = closure.everywhere(closure.trained_blob())
+    g = lbm.LBM(w.nx, w.ny, w.nz, storage, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi,
+                u_wall=w.u_wall)
+    g.set_canopy(w.cd, lad, False)
+    rho, u = inputs.init_fields_torch(w, torch.device("cuda"), seed=13)
+    g.init(rho, u)
+    del rho, u
+    g.step(20)
+    g.set_closure(blob)
+    o = ref.RefLBM(w.nx, w.ny, SLAB, w.tau0, w.c_smag, w.g, w.bc_lo, w.bc_hi)
+    o.set_wall_velocity(w.u_wall)
+    o.set_canopy(w.cd, lad, False)
+    o.set_closure(ref.MLP(blob))
+    slab = g.get_f()[:, K0:K0 + SLAB].copy()
+    for parity in (0, 1):
+        o.set_f(slab)
+        o.step(1)
+        g.step(1)
+        full = g.get_f()
+        _, _, ng, dg = g.moments()
+        ng = ng[K0 + 1:K0 + SLAB - 1]
+        sg = full[:, K0 + 1:K0 + SLAB - 1] - W4
+        shifted_in = slab[:, 1:SLAB - 1] - W4
+        slab = full[:, K0:K0 + SLAB].copy()
+        del full
+        fo = o.get_f()
+        _, _, no, do = o.moments()
+        so = fo[:, 1:SLAB - 1] - W4
+        no = no[1:SLAB - 1]
+        assert dg["mlp_fallback"] == 0 and do["mlp_fallback"] == 0
+        e_nut = float(np.max(np.abs(ng - no)) / np.max(np.abs(no)))
+        dnu = 3e-2 * np.max(np.abs(no))
+        tau = w.tau0
+        relax = 2 * np.max(np.abs(shifted_in)) * 3 * dnu / tau ** 2
+        bound = ulp(so, storage) + 8 * 2.0 ** -24 * W4 + relax
+        worst = float(np.max(np.abs(sg - so) / bound))
+        print("learned parity", parity, "nu_t normwise", e_nut, "max nu_t", float(np.max(no)),
+              "populations max err/bound", worst)
+        assert e_nut <= 3e-2
+        assert worst <= 1.0
+        np.testing.assert_array_equal(round_storage(sg, storage), sg)
+    g.close()
