@@ -337,22 +337,20 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     // cache lines (350x140x280: +7 %).  The switch is at 96 MiB.
     // LBMX_TILE_ORDER=0/1 overrides.
     c->memorder = !c->streaming || (unsigned long long)c->qs * c->elt > (96ULL << 20);
-    // FP32 and FP64 arrays beyond the Infinity Cache: memory order, the
-    // XCDs taking turns in short runs of tiles (2 for FP32, 4 for FP64), so
-    // that they work side by side in one stretch of each plane instead of in
-    // eight distant ones.  Against the better of the two orders with one
-    // contiguous range per XCD: +4.8 % (FP32) and +6.6 % (FP64) at
-    // 512x128x256, +4.3 % at 1024x256x512, +3.6 / +4.6 % at 350x140x280,
-    // +7.5 / +9 % at 250x100x200 with single tiles taking turns.  Runs of 1
-    // to 16 tiles: these lengths came within 1 % of the best at 512x128x256,
-    // 1024x256x512, 350x140x280 and 250x100x200 (single tiles: FP32 -1.6 %
-    // at 512x128x256 and -2 % at 350x140x280, FP64 -6 % at 1024x256x512;
-    // runs of 8: FP32 -3.7 % at 1024x256x512).  The 16-bit types measured best with the choice
-    // above and one range per XCD (within 1 % of memory order with runs of
-    // 16; up to 10 % slower with single tiles), and so did FP32 on arrays
-    // that fit the cache (200x80x160).  The learned-closure kernel keeps its
-    // remapped walk.  LBMX_TILE_ORDER=0/1, LBMX_XCD_REMAP=0/1 and
-    // LBMX_XCD_RUN=tiles override.
+    // FP32 and FP64 arrays beyond the Infinity Cache: memory order, with the
+    // XCDs taking turns in short runs of consecutive tiles (2 for FP32, 4 for
+    // FP64), so that they work side by side in one stretch of each plane
+    // instead of in eight distant ones.  Measured against the better order
+    // with one contiguous range per XCD, single tiles taking turns gained
+    // 4.8 % (FP32) and 6.6 % (FP64) at 512x128x256, 4.3 % at 1024x256x512,
+    // 3.6 / 4.6 % at 350x140x280 and 7.5 / 9 % at 250x100x200.  Of runs of
+    // 1 to 16 tiles, the chosen lengths came within 1 % of the best on each
+    // of these grids (single tiles: FP32 -1.6 % at 512x128x256, FP64 -6 % at
+    // 1024x256x512; runs of 8: FP32 -3.7 % at 1024x256x512).  The 16-bit
+    // types measured best with the choice above and one range per XCD, and
+    // so did FP32 on arrays that fit the cache (200x80x160).  The
+    // learned-closure kernel keeps its remapped walk.  LBMX_TILE_ORDER=0/1,
+    // LBMX_XCD_REMAP=0/1 and LBMX_XCD_RUN=tiles override.
     c->xcd_remap = true;
     if (large_array(p) && c->elt >= 4) {
         c->memorder = true;
