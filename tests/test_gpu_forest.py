@@ -147,3 +147,36 @@ def test_forest_errors():
     assert e.value.status == 1
     with pytest.raises(lbm.LBMError):
         g.set_forest(0.2, float("nan"), np.zeros((4, 4, 8), dtype=np.uint32))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16sr"])
+def test_forest_padded_rows_change_nothing(monkeypatch, storage):
+    """Rows padded to whole lines (LBMX_PITCH=1) on a forest grid of 70
+    cells per row: the lanes on the pad cells store there, and the forest
+    table index of a cell is read through its dense index, which a pad lane
+    clamps to the row's last cell.  Populations and moments are bit for bit
+    those of dense rows; with the learned closure evaluated every 3rd step
+    too (the steps between read and the evaluating steps write the nu_t
+    plane)."""
+    from paper_2206_15454_amd import closure
+
+    w = inputs.scaled(inputs.FOREST, 70, 12, 9, storage=storage,
+                      forest=(1.0 / 30.0, 5.0, 9.0, 0.36, 0.7, 4.0))
+    blob = closure.timing_blob(10.0)
+    res = []
+    for pitch in ("0", "1"):
+        monkeypatch.setenv("LBMX_PITCH", pitch)
+        out = []
+        for learned in (False, True):
+            _, g, _ = make_forest_pair(w, seed=3)
+            if learned:
+                g.set_closure(blob)
+                g.set_closure_interval(3)
+            g.step(8)
+            r, u, nt, d = g.moments()
+            out.append((g.get_f(), r, u, nt, d["mlp_fallback"]))
+            g.close()
+        res.append(out)
+    for a, b in zip(res[0], res[1]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
