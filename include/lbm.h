@@ -119,7 +119,7 @@ size_t lbm_required_bytes(const lbm_params *p);
  * variables read at this call override them (for tests and tuning; the
  * populations are bit-identical under every choice, FP64 diagnostic sums
  * may differ in their last bits through the summation order):
- *   LBMX_BX=32|64|128|256   tile width in x (default: the widest of 256, 128,
+ *   LBMX_BX=64|128|256      tile width in x (default: the widest of 256, 128,
  *                           64 that pads a row least)
  *   LBMX_ZALIGN=bytes       population z-layers (px ny cells) rounded up to a
  *   LBMX_ZPAD=bytes         multiple of, or widened by, this many bytes (a

@@ -125,8 +125,12 @@ bool valid_params(const lbm_params *p, std::string *why) {
 // launch geometry: tiles of BX x 1 x BZ cells (BX*BZ = 256), one row each.
 // BX is the widest of 256/128/64 that pads a row least (idle lanes of a
 // ragged last tile cost bandwidth: 350 cells in 256-wide tiles leave 32% of
-// the lanes idle, in 128-wide tiles 9%).  32-wide tiles (LBMX_BX=32 only)
-// pad less but were measured slower: their short rows split cache lines.
+// the lanes idle, in 128-wide tiles 9%).  32-wide tiles, which pad less, were
+// measured slower (their short rows split cache lines) and are not offered:
+// the step takes a wave's z row as uniform, which needs tiles of 64 cells or
+// more.  Narrow tiles are slower than 256-wide ones at equal work
+// (512x140x280 FP32: 0.699 of the roofline in 128-wide tiles against 0.733;
+// tiles of two adjacent y rows instead of two z rows measured the same).
 // Packing the tails of several rows into one wave (350 cells in 5.5 waves
 // instead of 6) was built and measured: no faster at 350x140x280, slower
 // for FP32 at 200x80x160 (a wave of eight 8-cell tails touches eight
@@ -143,7 +147,7 @@ void geometry(const lbm_params *p, int *bx, int *bz, int *nbx, int *nbz) {
     }
     if (const char *e = std::getenv("LBMX_BX")) {
         int v = std::atoi(e);
-        if (v == 32 || v == 64 || v == 128 || v == 256) BX = v;
+        if (v == 64 || v == 128 || v == 256) BX = v;
     }
     *bx = BX;
     *bz = 256 / BX;

@@ -113,7 +113,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
         bz = rest - j * a.nbz;
     }
     const int i = bx * (int)blockDim.x + (int)threadIdx.x;
-    const int k = bz * (int)blockDim.y + (int)threadIdx.y;
+    // the z row: uniform per wave (tiles are 64, 128 or 256 cells wide); the
+    // plain step holds it, and so its z offsets, in scalar registers (+1.3 %
+    // for FP32 at 512x128x256); the learned-closure kernel, whose scalar
+    // registers are full, keeps them in vector registers (held in scalar
+    // ones, they tripled its spills to vector lanes)
+    const int kv = bz * (int)blockDim.y + (int)threadIdx.y;
+    const int k = LEARNED ? kv : __builtin_amdgcn_readfirstlane(kv);
     const bool active = (i < nx) && (k < nz);
     const int ic = i < nx ? i : nx - 1;  // clamped: inactive lanes load valid memory
     // pad lanes (on a padded row's cells nx <= i < px) load and store their
@@ -934,7 +940,7 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
     }
 
 hipError_t launch_step(int storage, const StepArgs &a, int bx, int bz, hipStream_t s) {
-    if (bx * bz != 256 || a.ntiles < 1) return hipErrorInvalidValue;
+    if (bx * bz != 256 || bx % 64 != 0 || a.ntiles < 1) return hipErrorInvalidValue;
     dim3 block(bx, bz), grid(a.ntiles);
     LBMX_DISPATCH(storage, LBMX_VARIANT(a.flags, hipLaunchKernelGGL((lbm_step_kernel<S, V>), grid,
                                                                     block, 0, s, a)));
@@ -959,7 +965,8 @@ hipError_t mlp_launch_grid(int storage, int flags, int ntiles, int *grid) {
 
 hipError_t launch_step_mlp(int storage, const StepArgs &a, int bx, int bz, int grid,
                            hipStream_t s) {
-    if (bx * bz != 256 || a.ntiles < 1 || a.mlp == nullptr || grid < 1 || grid > a.ntiles)
+    if (bx * bz != 256 || bx % 64 != 0 || a.ntiles < 1 || a.mlp == nullptr || grid < 1 ||
+        grid > a.ntiles)
         return hipErrorInvalidValue;
     if (a.flags & FLAG_NUT_IN) return hipErrorInvalidValue;  // the network computes nu_t
     LBMX_DISPATCH(storage, LBMX_VARIANT_MLP(a.flags, hipLaunchKernelGGL((lbm_step_mlp_kernel<S, V>),

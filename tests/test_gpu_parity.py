@@ -172,17 +172,27 @@ def test_checkpoint_roundtrip_is_bit_identical():
 
 
 def test_tile_width_does_not_change_fp64_results(monkeypatch):
+    """Tiles 64, 128 or 256 cells wide (covering 4, 2 or 1 z rows of a row
+    j; 300x6x5 leaves the last z block ragged), with and without the XCD
+    remap: bit-identical FP64 populations, and the plane statistics, which
+    each tile sums over its cells, equal up to their FP64 summation order."""
     w = inputs.scaled(inputs.C1, 300, 6, 5)
-    res = []
-    for bx in ("32", "64", "128", "256"):
+    res, stats = [], []
+    for bx in ("64", "128", "256"):
         monkeypatch.setenv("LBMX_BX", bx)
         for remap in ("0", "1"):
             monkeypatch.setenv("LBMX_XCD_REMAP", remap)
             _, g = make_pair(w, seed=4)
+            g.stats_reset()
+            g.stats_enable(3)
             g.step(12)
             res.append(g.get_f())
+            stats.append(g.stats_read())
     for r in res[1:]:
         np.testing.assert_array_equal(r, res[0])
+    for p, n in stats[1:]:
+        assert n == stats[0][1] == 4
+        np.testing.assert_allclose(p, stats[0][0], rtol=1e-12, atol=1e-18)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16sr"])
