@@ -144,6 +144,11 @@ size_t lbm_required_bytes(const lbm_params *p);
  *   LBMX_FX=0|1             kernels that leave out the y and z force terms
  *                           when g_y = g_z = 0 and the drag is x-only
  *                           (default 1)
+ *   LBMX_MLP_SPLIT=0|1      a step that evaluates the learned closure runs
+ *                           the network's kernel on the rows whose y/h lies
+ *                           in the closure's range and the plain step on the
+ *                           others, whose cells all fall back (default 1;
+ *                           0: the network's kernel on every row)
  *   LBMX_PITCH=0|1          population rows padded to whole 128-byte lines
  *                           (default: for population arrays above 256 MiB,
  *                           rows of nx cells that are not whole lines get a

@@ -71,6 +71,9 @@ struct lbm_ctx {
     int closure_lag = 0;     // steps since its last evaluation (0: evaluate next)
     int64_t evals = 0;       // evaluations so far (fallback counter slot = evals & 1)
     int last_fb_slot = 0;    // slot of the last evaluation
+    int64_t fb_rows_cells = 0;  // cells of the rows the last evaluation gave the plain step
+    bool mlp_split = true;   // evaluating steps: network rows in the learned kernel, the rest
+                             // in the plain step (LBMX_MLP_SPLIT=0: one learned launch)
     MlpConst mc{};           // learned closure scalars (kernel arguments)
     int mlp_grid[8] = {};    // persistent grid of the learned-closure kernel per variant
     bool diag_fresh = false; // dg holds the diagnostics of the moments lbm_moments reads
@@ -328,6 +331,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
     c->ntiles = c->tpp * p->ny;
     if (const char *e = std::getenv("LBMX_WIDE")) c->force_wide = std::atoi(e) != 0;
     if (const char *e = std::getenv("LBMX_FX")) c->fx = std::atoi(e) != 0;
+    if (const char *e = std::getenv("LBMX_MLP_SPLIT")) c->mlp_split = std::atoi(e) != 0;
     // streaming (non-temporal) accesses for arrays beyond the Infinity Cache
     // whose rows are whole 128-byte lines (the planes start on 256-byte
     // boundaries); LBMX_STREAMING=0/1 overrides
@@ -501,6 +505,7 @@ lbm_status lbm_set_closure(lbm_ctx *c, int32_t closure, const void *blob, size_t
     c->mc = mc;
     c->closure_lag = 0;
     c->evals = 0;
+    c->fb_rows_cells = 0;
     c->last_fb_slot = 0;
     return LBM_OK;
 }
@@ -562,6 +567,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     a.nbz = c->nbz;
     div_magic((uint32_t)a.nbx, &a.m_nbx, &a.s_nbx);
     div_magic((uint32_t)a.nbz, &a.m_nbz, &a.s_nbz);
+    a.j0 = 0;
+    a.nrows = c->p.ny;
     div_magic((uint32_t)c->p.ny, &a.m_ny, &a.s_ny);
     a.ntiles = c->ntiles;
     a.xcd_run = c->xcd_run;
@@ -626,15 +633,61 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
             a.flags |= FLAG_NUT_IN;
         }
         hipError_t e = hipSuccess;
-        if (evaluate) {
+        // one launch over the rows j0 .. j0 + nrows - 1, whose tiles take the
+        // records from tile 'off' on (the launches of a step fill them once)
+        auto launch_rows = [&](StepArgs r, int j0, int nrows, long long off, bool mlp) {
+            r.j0 = j0;
+            r.nrows = nrows;
+            div_magic((uint32_t)nrows, &r.m_ny, &r.s_ny);
+            r.ntiles = c->nbx * c->nbz * nrows;
+            r.imp = c->imp + 12 * off;
+            r.dg = c->dg + 24 * off;
+            if (!mlp) {
+                r.flags &= ~FLAG_MLP;
+                r.flags = (r.flags & ~FLAG_WIDE) | (base_flags & FLAG_WIDE);
+                r.flags = c->xcd_remap ? (r.flags | FLAG_XCD_REMAP) : (r.flags & ~FLAG_XCD_REMAP);
+                return launch_step(c->p.storage, r, c->bx, c->bz, c->stream);
+            }
             // the persistent grid depends on the kernel variant only: the
             // occupancy query runs once per variant and context
-            const int v = ((a.flags & FLAG_FOREST) ? 1 : 0) | ((a.flags & FLAG_WIDE) ? 2 : 0) |
-                          ((a.flags & FLAG_FX) ? 4 : 0);
+            const int v = ((r.flags & FLAG_FOREST) ? 1 : 0) | ((r.flags & FLAG_WIDE) ? 2 : 0) |
+                          ((r.flags & FLAG_FX) ? 4 : 0);
+            hipError_t e2 = hipSuccess;
             if (c->mlp_grid[v] == 0)
-                e = mlp_launch_grid(c->p.storage, a.flags, c->ntiles, &c->mlp_grid[v]);
-            if (e == hipSuccess)
-                e = launch_step_mlp(c->p.storage, a, c->bx, c->bz, c->mlp_grid[v], c->stream);
+                e2 = mlp_launch_grid(c->p.storage, r.flags, c->ntiles, &c->mlp_grid[v]);
+            if (e2 != hipSuccess) return e2;
+            const int grid = std::min(c->mlp_grid[v], r.ntiles);
+            return launch_step_mlp(c->p.storage, r, c->bx, c->bz, grid, c->stream);
+        };
+        if (evaluate) {
+            // Rows whose y/h lies outside the network's trained range fall
+            // back to Smagorinsky in every cell: the plain step takes them
+            // (bit for bit the learned kernel's fallback, at the plain step's
+            // rate), the learned kernel the rows in between.  The test is the
+            // kernel's own, in FP32.
+            int ja = 0, jb = c->p.ny;
+            if (c->mlp_split) {
+                ja = c->p.ny;
+                jb = 0;
+                for (int j = 0; j < c->p.ny; ++j) {
+                    const float yh = ((float)j + 0.5f) * c->mc.inv_h;
+                    if (yh >= c->mc.lo[6] && yh <= c->mc.hi[6]) {
+                        ja = std::min(ja, j);
+                        jb = j + 1;
+                    }
+                }
+                if (ja >= jb) {  // no row in range: one learned launch as usual
+                    ja = 0;
+                    jb = c->p.ny;
+                }
+            }
+            const long long rows_tiles = (long long)c->nbx * c->nbz;
+            e = launch_rows(a, ja, jb - ja, 0, true);
+            if (e == hipSuccess && ja > 0)
+                e = launch_rows(a, 0, ja, rows_tiles * (jb - ja), false);
+            if (e == hipSuccess && jb < c->p.ny)
+                e = launch_rows(a, jb, c->p.ny - jb, rows_tiles * jb, false);
+            c->fb_rows_cells = (long long)(c->p.ny - (jb - ja)) * c->p.nx * c->p.nz;
         } else {
             e = launch_step(c->p.storage, a, c->bx, c->bz, c->stream);
         }
@@ -695,6 +748,7 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, double *nut, int32_t 
     if (c->closure == LBM_CLOSURE_MLP) {
         lbm_status s = mlp_fallback_count(c->mlp, c->last_fb_slot, &fb, c->stream);
         if (s != LBM_OK) return fail(c, s, "lbm_moments: fallback count");
+        fb += c->fb_rows_cells;  // the rows outside the network's range
     }
     if (d) {
         d->mass = out[0];

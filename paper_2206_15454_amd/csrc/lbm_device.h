@@ -304,10 +304,11 @@ struct StepArgs {
     int px;           // population row pitch (cells, >= nx)
     int zp;           // population z-layer pitch (cells, >= px ny): cell (i,j,k) at k zp + j px + i
     int nbx, nbz;     // tiles per row (x) and per column (z); tile = BX x 1 x BZ cells
-    // division by nbx, nbz and ny as multiply and shift (div_magic)
+    int j0, nrows;    // the launch covers rows j0 .. j0 + nrows - 1 (all: 0, ny)
+    // division by nbx, nbz and nrows as multiply and shift (div_magic)
     uint32_t m_nbx, m_nbz, m_ny;
     int s_nbx, s_nbz, s_ny;
-    int ntiles;       // nbx * nbz * ny = grid size
+    int ntiles;       // nbx * nbz * nrows = grid size
     int xcd_run;      // FLAG_XCD_REMAP: 0 = one contiguous range per XCD, else runs of this many tiles
     int parity;       // 0: neighbour step, 1: local step (in-place AA pattern)
     int bc_lo, bc_hi;
@@ -326,8 +327,10 @@ struct StepArgs {
     const double *ftab;    // LAD of each forest table entry; entry 0 is 0
     const float *ftabf;    // the same in FP32 (FP32 arithmetic)
     void *mom;        // moments in the arithmetic type: rho, ux, uy, uz, nu_t planes of N
-    double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront)
-    double *dg;       // [ntiles][4][6] diagnostics of the last FLAG_MOMENTS step (per wavefront)
+    double *imp;      // [ntiles][4][3] body-force impulse accumulators (per wavefront; this
+                      // launch's share when a step is split over row ranges)
+    double *dg;       // [ntiles][4][6] diagnostics of the last FLAG_MOMENTS step (per
+                      // wavefront; likewise)
     double *stats;    // [ny][nbx*nbz][10] statistics accumulators
     const void *mlp;  // learned closure parameters on the device
     MlpConst mc;      // learned closure scalars (FLAG_MLP)

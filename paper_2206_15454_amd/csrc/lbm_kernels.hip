@@ -107,11 +107,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const int tile, con
     int j, bz;  // the whole block lies in row j
     if (LEARNED || (a.flags & FLAG_MEMORDER) != 0) {
         bz = (int)div_by((uint32_t)rest, a.m_ny, a.s_ny);
-        j = rest - bz * ny;
+        j = rest - bz * a.nrows;
     } else {
         j = (int)div_by((uint32_t)rest, a.m_nbz, a.s_nbz);
         bz = rest - j * a.nbz;
     }
+    j += a.j0;  // the launch's rows
     const int i = bx * (int)blockDim.x + (int)threadIdx.x;
     // the z row: uniform per wave (tiles are 64, 128 or 256 cells wide); the
     // plain step holds it, and so its z offsets, in scalar registers (+1.3 %

@@ -319,3 +319,39 @@ def test_learned_kernel_statistics_equal_plain_when_every_cell_falls_back():
     np.testing.assert_array_equal(a.get_f(), b.get_f())
     np.testing.assert_array_equal(pb[:, :9], pa[:, :9])
     assert np.max(np.abs(pb[:, 9] - pa[:, 9]) / np.maximum(np.abs(pa[:, 9]), 1e-30)) <= 1e-6
+
+
+@pytest.mark.parametrize("storage,every", [("f32", 1), ("bf16sr", 1), ("bf16sr", 3)])
+def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, storage, every):
+    """The trained network restricted to the canopy layer (y/h <= 4 through
+    its feature range) on 128x64x16, h = 12: the evaluating steps run the
+    learned kernel on the rows whose y/h is in range and the plain step on
+    the rows above, whose cells would all fall back (LBMX_MLP_SPLIT=0: one
+    learned launch over every row).  Populations, moments, nu_t and the
+    fallback count are bit for bit the same, every step and with the
+    network every 3rd step; the plane statistics and FP64 diagnostics agree
+    up to their summation order (the impulse of the plain rows is summed per
+    wave in FP32 instead of per thread in FP64)."""
+    w = inputs.scaled(inputs.C2, 128, 64, 16)
+    blob = closure.canopy_layer_blob()
+    runs = []
+    for split in ("0", "1"):
+        monkeypatch.setenv("LBMX_MLP_SPLIT", split)
+        _, g = make_pair(w, storage=storage, seed=14)
+        g.set_closure(blob)
+        g.set_closure_interval(every)
+        g.stats_reset()
+        g.stats_enable(2)
+        g.step(9)
+        runs.append((g.get_f(), g.moments(), g.stats_read()))
+        g.close()
+    (f0, m0, (p0, n0)), (f1, m1, (p1, n1)) = runs
+    np.testing.assert_array_equal(f1, f0)
+    for x, y in zip(m0[:3], m1[:3]):
+        np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+    assert m1[3]["mlp_fallback"] == m0[3]["mlp_fallback"] > 0
+    for key, v in m0[3].items():
+        rtol = 1e-5 if key.startswith("imp") and storage != "f64" else 1e-12
+        np.testing.assert_allclose(m1[3][key], v, rtol=rtol, atol=1e-300)
+    assert n0 == n1 == 4
+    np.testing.assert_allclose(p1, p0, rtol=1e-12, atol=1e-18)
