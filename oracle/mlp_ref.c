@@ -17,7 +17,12 @@
  *     o = w3 . h2 + b3, nu_t = s * softplus(o)
  *   gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3)))
  *   fallback: if any raw feature lies outside [lo_i, hi_i], nu_t is the
- *     Smagorinsky value.
+ *     Smagorinsky value.  The bounds are FP32 numbers and the test is taken
+ *     in FP32 on the feature rounded to FP32: a yes/no decision that a
+ *     floating-point comparison makes is made in the same precision on both
+ *     sides (the kernel's; the bounds come from the training data, where
+ *     the extreme values, such as the LAD of the densest row, are the
+ *     bounds themselves).
  *   loss for training: mean over the batch of (softplus(o) - y)^2, with y the
  *     target nu_t / s.
  *
@@ -224,11 +229,13 @@ int ref_mlp_features(const struct mlp_ref *m, double tau0, double rho, const dou
  * outside the stored range */
 double ref_mlp_closure_nut(const struct mlp_ref *m, const double *x, int *used_fallback,
                            double smag_nut) {
-    for (int i = 0; i < NIN; ++i)
-        if (!(x[i] >= m->lo[i] && x[i] <= m->hi[i])) {
+    for (int i = 0; i < NIN; ++i) {
+        const float xf = (float)x[i];
+        if (!(xf >= (float)m->lo[i] && xf <= (float)m->hi[i])) {
             *used_fallback = 1;
             return smag_nut;
         }
+    }
     double z[NIN];
     for (int i = 0; i < NIN; ++i) z[i] = (x[i] - m->mean[i]) / m->std[i];
     double o = net(m->p, z, NULL, NULL);

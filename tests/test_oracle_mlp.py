@@ -119,6 +119,16 @@ def test_blob_roundtrip_and_fallback():
     o = ref.mlp_apply(p, Zs)
     np.testing.assert_allclose(nut[1:], float(np.float32(1e-4)) * np.log1p(np.exp(o)),
                                rtol=1e-12)
+    # the range test is taken in FP32: a feature just above an FP32 bound in
+    # FP64 that rounds onto it is inside; one that rounds above it is outside
+    top = float(np.float32(5.0))
+    ulp32 = float(np.spacing(np.float32(5.0)))
+    X2 = np.tile(X[1], (3, 1))
+    X2[0, 4] = top + 0.25 * ulp32  # rounds to 5.0: in range
+    X2[1, 4] = top + 0.75 * ulp32  # rounds to the next FP32 number: out
+    X2[2, 4] = -top - 0.25 * ulp32  # rounds to -5.0: in range
+    _, fb2 = m.predict(X2, smag[:3])
+    assert fb2.tolist() == [0, 1, 0]
     with pytest.raises(ValueError):
         ref.MLP(blob[:-2])
     with pytest.raises(ValueError):
