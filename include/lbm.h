@@ -149,6 +149,12 @@ size_t lbm_required_bytes(const lbm_params *p);
  *                           in the closure's range and the plain step on the
  *                           others, whose cells all fall back (default 1;
  *                           0: the network's kernel on every row)
+ *   LBMX_MLP_OVERLAP=N      with that split, the plain rows run on a second
+ *                           stream of the library's beside the network's
+ *                           kernel, which takes N blocks per CU (default 2;
+ *                           0: one stream, the launches in turn).  The
+ *                           caller's stream waits for both; results are the
+ *                           same bit for bit
  *   LBMX_PITCH=0|1          population rows padded to whole 128-byte lines
  *                           (default: for population arrays above 256 MiB,
  *                           rows of nx cells that are not whole lines get a

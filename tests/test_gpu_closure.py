@@ -327,7 +327,9 @@ def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, stor
     its feature range) on 128x64x16, h = 12: the evaluating steps run the
     learned kernel on the rows whose y/h is in range and the plain step on
     the rows above, whose cells would all fall back (LBMX_MLP_SPLIT=0: one
-    learned launch over every row).  Populations, moments, nu_t and the
+    learned launch over every row), in turn on one stream or with the plain
+    rows on the library's second stream beside the network's kernel
+    (LBMX_MLP_OVERLAP=2, the default).  Populations, moments, nu_t and the
     fallback count are bit for bit the same, every step and with the
     network every 3rd step; the plane statistics and FP64 diagnostics agree
     up to their summation order (the impulse of the plain rows is summed per
@@ -335,8 +337,11 @@ def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, stor
     w = inputs.scaled(inputs.C2, 128, 64, 16)
     blob = closure.canopy_layer_blob()
     runs = []
-    for split in ("0", "1"):
+    # (split, overlap): one learned launch; the split in turn on one stream;
+    # the split with the plain rows on the second stream beside the network
+    for split, overlap in (("0", "0"), ("1", "0"), ("1", "2")):
         monkeypatch.setenv("LBMX_MLP_SPLIT", split)
+        monkeypatch.setenv("LBMX_MLP_OVERLAP", overlap)
         _, g = make_pair(w, storage=storage, seed=14)
         g.set_closure(blob)
         g.set_closure_interval(every)
@@ -345,13 +350,19 @@ def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, stor
         g.step(9)
         runs.append((g.get_f(), g.moments(), g.stats_read()))
         g.close()
-    (f0, m0, (p0, n0)), (f1, m1, (p1, n1)) = runs
-    np.testing.assert_array_equal(f1, f0)
-    for x, y in zip(m0[:3], m1[:3]):
-        np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
-    assert m1[3]["mlp_fallback"] == m0[3]["mlp_fallback"] > 0
-    for key, v in m0[3].items():
-        rtol = 1e-5 if key.startswith("imp") and storage != "f64" else 1e-12
-        np.testing.assert_allclose(m1[3][key], v, rtol=rtol, atol=1e-300)
-    assert n0 == n1 == 4
-    np.testing.assert_allclose(p1, p0, rtol=1e-12, atol=1e-18)
+    (f0, m0, (p0, n0)) = runs[0]
+    for f1, m1, (p1, n1) in runs[1:]:
+        np.testing.assert_array_equal(f1, f0)
+        for x, y in zip(m0[:3], m1[:3]):
+            np.testing.assert_array_equal(np.asarray(y), np.asarray(x))
+        assert m1[3]["mlp_fallback"] == m0[3]["mlp_fallback"] > 0
+        for key, v in m0[3].items():
+            rtol = 1e-5 if key.startswith("imp") and storage != "f64" else 1e-12
+            np.testing.assert_allclose(m1[3][key], v, rtol=rtol, atol=1e-300)
+        assert n0 == n1 == 4
+        np.testing.assert_allclose(p1, p0, rtol=1e-12, atol=1e-18)
+    # the two split runs differ only in the streams: bit for bit the same
+    # diagnostics and statistics as well
+    (_, ma, (pa, _)), (_, mb, (pb, _)) = runs[1], runs[2]
+    assert ma[3] == mb[3]
+    np.testing.assert_array_equal(pb, pa)
