@@ -253,7 +253,11 @@ lbm_status lbm_set_closure_interval(lbm_ctx *ctx, int32_t every);
  * read back before the first step are rho, u and nu_t = 0.  EINVAL for NULL. */
 lbm_status lbm_init(lbm_ctx *ctx, const double *rho, const double *u, int32_t on_device);
 
-/* Enqueue n >= 0 time steps, one fused kernel launch each, asynchronously.
+/* Enqueue n >= 0 time steps, one fused kernel launch each, asynchronously
+ * on the context's stream (a step that evaluates a learned closure whose y/h
+ * range leaves out rows takes two or three launches, the rows outside it on
+ * a second stream of the library's that the context's stream waits for; see
+ * LBMX_MLP_SPLIT and LBMX_MLP_OVERLAP).
  * One step is the time loop body of Algorithm 1 (alg:forestGASCANS): stream
  * (Sec. 2.1, Eq. lbe; walls of Sec. 4 and Sec. 5.1), velocity (Eqs. density,
  * momentum), forest force and corrected velocity (Sec. 2.3, Eq.
