@@ -321,8 +321,9 @@ def test_learned_kernel_statistics_equal_plain_when_every_cell_falls_back():
     assert np.max(np.abs(pb[:, 9] - pa[:, 9]) / np.maximum(np.abs(pa[:, 9]), 1e-30)) <= 1e-6
 
 
-@pytest.mark.parametrize("storage,every", [("f32", 1), ("bf16sr", 1), ("bf16sr", 3)])
-def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, storage, every):
+@pytest.mark.parametrize("storage,every,yh_lo", [("f32", 1, None), ("bf16sr", 1, None),
+                                                 ("bf16sr", 3, None), ("f16s", 1, 1.0)])
+def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, storage, every, yh_lo):
     """The trained network restricted to the canopy layer (y/h <= 4 through
     its feature range) on 128x64x16, h = 12: the evaluating steps run the
     learned kernel on the rows whose y/h is in range and the plain step on
@@ -331,11 +332,14 @@ def test_row_split_of_the_canopy_layer_closure_changes_nothing(monkeypatch, stor
     rows on the library's second stream beside the network's kernel
     (LBMX_MLP_OVERLAP=2, the default).  Populations, moments, nu_t and the
     fallback count are bit for bit the same, every step and with the
-    network every 3rd step; the plane statistics and FP64 diagnostics agree
+    network every 3rd step, and with the range starting at y/h = 1 (plain
+    rows below and above the network's); the plane statistics and FP64 diagnostics agree
     up to their summation order (the impulse of the plain rows is summed per
     wave in FP32 instead of per thread in FP64)."""
     w = inputs.scaled(inputs.C2, 128, 64, 16)
     blob = closure.canopy_layer_blob()
+    if yh_lo is not None:  # rows below the range too: plain launches on both sides
+        blob = closure.with_range(blob, "y_over_h", lo=yh_lo)
     runs = []
     # (split, overlap): one learned launch; the split in turn on one stream;
     # the split with the plain rows on the second stream beside the network
