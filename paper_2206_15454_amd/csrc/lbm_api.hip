@@ -85,6 +85,7 @@ struct lbm_ctx {
     // BF16SR 39.1k -> 44.0k MLUPS, F16S 41.2k -> 46.6k (one block per CU
     // 31.7k, three 43.0k)
     int mlp_overlap = 2;
+    int ncu = 0;  // compute units (queried with the second stream, once)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool diag_fresh = false; // dg holds the diagnostics of the moments lbm_moments reads
@@ -709,18 +710,29 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
             hipStream_t ps = c->stream;
             int cap = 0;
             if (overlap) {
-                if (!c->side) {
-                    e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-                    if (e != hipSuccess) return hip_fail(c, e, "lbm_step: second stream");
+                if (!c->side) {  // set up once; kept only when every part succeeded
+                    hipStream_t st = nullptr;
+                    hipEvent_t ef = nullptr, ej = nullptr;
+                    int ncu = 0;
+                    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+                    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+                    if (e == hipSuccess) e = hipEventCreateWithFlags(&ef, hipEventDisableTiming);
+                    if (e == hipSuccess) e = hipEventCreateWithFlags(&ej, hipEventDisableTiming);
+                    if (e != hipSuccess) {
+                        if (ej) (void)hipEventDestroy(ej);
+                        if (ef) (void)hipEventDestroy(ef);
+                        if (st) (void)hipStreamDestroy(st);
+                        return hip_fail(c, e, "lbm_step: second stream");
+                    }
+                    c->side = st;
+                    c->ev_fork = ef;
+                    c->ev_join = ej;
+                    c->ncu = ncu;
                 }
-                int ncu = 0;
-                e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-                if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
+                e = hipEventRecord(c->ev_fork, c->stream);
                 if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
                 if (e != hipSuccess) return hip_fail(c, e, "lbm_step: fork");
-                cap = std::max(8, c->mlp_overlap * ncu / 8 * 8);
+                cap = std::max(8, c->mlp_overlap * c->ncu / 8 * 8);
                 ps = c->side;
             }
             e = launch_rows(a, ja, jb - ja, 0, true, c->stream, cap);
