@@ -437,15 +437,15 @@ lbm_status lbm_create(const lbm_params *p, void *dev_buf, size_t dev_bytes, lbm_
 
 lbm_status lbm_destroy(lbm_ctx *c) {
     if (!c) return LBM_EINVAL;
-    if (c->owns && c->base) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->base);
-    }
-    if (c->side) {
+    if (c->side) {  // the second stream's work ends before the memory goes
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
         (void)hipEventDestroy(c->ev_fork);
         (void)hipEventDestroy(c->ev_join);
+    }
+    if (c->owns && c->base) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->base);
     }
     delete c;
     return LBM_OK;
@@ -740,9 +740,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
                 e = launch_rows(a, 0, ja, rows_tiles * (jb - ja), false, ps, 0);
             if (e == hipSuccess && jb < c->p.ny)
                 e = launch_rows(a, jb, c->p.ny - jb, rows_tiles * jb, false, ps, 0);
-            if (e == hipSuccess && overlap) {
-                e = hipEventRecord(c->ev_join, c->side);
-                if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+            if (overlap) {  // joined after a failed launch too: no work left behind
+                hipError_t ej = hipEventRecord(c->ev_join, c->side);
+                if (ej == hipSuccess) ej = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+                if (e == hipSuccess) e = ej;
             }
             c->fb_rows_cells = (long long)(c->p.ny - (jb - ja)) * c->p.nx * c->p.nz;
         } else {
